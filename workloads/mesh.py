@@ -1,0 +1,101 @@
+"""Structured tetrahedral meshes of a cube (input data, not method).
+
+A cube [o, o+length]^3 is cut into n^3 sub-cubes; every sub-cube is split into
+the six Kuhn (Freudenthal) tetrahedra that share its main diagonal
+(0,0,0)->(1,1,1).  Every sub-cube uses the same split, so the mesh is conforming
+and periodic-compatible.
+
+Conventions shared with the library interface (``include/dgd.h``):
+
+* ``tets[e] = (v0, v1, v2, v3)`` is positively oriented:
+  det[x1-x0, x2-x0, x3-x0] > 0.
+* Face ``f`` of a tetrahedron is the face opposite local vertex ``3 - f``:
+  f0 = (v0, v2, v1), f1 = (v0, v1, v3), f2 = (v0, v3, v2), f3 = (v1, v2, v3)
+  (vertex triples ordered so that the right-hand normal points outward).
+* ``face_tag[e, f]``: -1 interior (or periodic), 1 free surface, 2 absorbing.
+* ``periodic_map[v]``: canonical vertex id that ``v`` is identified with (the
+  copy with every grid coordinate reduced modulo n); vertices on opposite
+  domain faces are glued through it.
+"""
+import itertools
+import math
+
+import numpy as np
+
+FACE_VERTS = ((0, 2, 1), (0, 1, 3), (0, 3, 2), (1, 2, 3))
+
+TAG_INTERIOR = -1
+TAG_FREE = 1
+TAG_ABSORB = 2
+
+
+def kuhn_inradius(edge):
+    """Inradius of a Kuhn tetrahedron of a cube with edge length ``edge``.
+
+    volume edge^3/6, total face area (1 + sqrt 2) edge^2, r = 3V/A.
+    """
+    return edge / (2.0 * (1.0 + math.sqrt(2.0)))
+
+
+def cube_mesh(n, length, periodic=False, origin=(0.0, 0.0, 0.0),
+              top_free=True):
+    """Return a dict with ``xyz`` (nv,3) f64, ``tets`` (ne,4) i64,
+    ``face_tag`` (ne,4) i8, ``periodic_map`` (nv,) i64 or None, ``n``,
+    ``length`` and ``edge``.
+
+    Non-periodic meshes tag the top face z = origin_z + length as free surface
+    (if ``top_free``) and the other five domain faces as absorbing.
+    """
+    n = int(n)
+    h = float(length) / n
+    o = np.asarray(origin, dtype=np.float64)
+    g = np.arange(n + 1)
+    # vertex id = i + (n+1)*(j + (n+1)*k)
+    kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
+    ijk = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    xyz = o[None, :] + h * ijk.astype(np.float64)
+
+    def vid(i, j, k):
+        return i + (n + 1) * (j + (n + 1) * k)
+
+    perms = list(itertools.permutations(range(3)))
+    tets = []
+    cells = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
+                                 indexing="ij"), axis=-1).reshape(-1, 3)
+    # cube order: i fastest, then j, then k
+    cells = cells[np.lexsort((cells[:, 0], cells[:, 1], cells[:, 2]))]
+    for (ci, cj, ck) in cells:
+        for p in perms:
+            path = [np.array([ci, cj, ck])]
+            cur = path[0].copy()
+            for ax in p:
+                cur = cur.copy()
+                cur[ax] += 1
+                path.append(cur)
+            ids = [vid(*c) for c in path]
+            # parity of the permutation decides the orientation
+            inv = sum(1 for a in range(3) for b in range(a + 1, 3) if p[a] > p[b])
+            if inv % 2 == 1:
+                ids[1], ids[2] = ids[2], ids[1]
+            tets.append(ids)
+    tets = np.asarray(tets, dtype=np.int64)
+
+    if periodic:
+        pm = vid(ijk[:, 0] % n, ijk[:, 1] % n, ijk[:, 2] % n).astype(np.int64)
+        face_tag = np.full((tets.shape[0], 4), TAG_INTERIOR, dtype=np.int8)
+    else:
+        pm = None
+        face_tag = np.full((tets.shape[0], 4), TAG_INTERIOR, dtype=np.int8)
+        vijk = ijk[tets]  # (ne, 4, 3)
+        for f, fv in enumerate(FACE_VERTS):
+            c = vijk[:, list(fv), :]  # (ne, 3, 3)
+            for ax in range(3):
+                on_lo = np.all(c[:, :, ax] == 0, axis=1)
+                on_hi = np.all(c[:, :, ax] == n, axis=1)
+                face_tag[on_lo, f] = TAG_ABSORB
+                if ax == 2 and top_free:
+                    face_tag[on_hi, f] = TAG_FREE
+                else:
+                    face_tag[on_hi, f] = TAG_ABSORB
+    return {"xyz": xyz, "tets": tets, "face_tag": face_tag,
+            "periodic_map": pm, "n": n, "length": float(length), "edge": h}
