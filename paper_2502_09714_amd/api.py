@@ -1,0 +1,188 @@
+"""Thin Python front end of the C interface (same names, argument marshalling).
+
+Host arrays are numpy float64/int64 arrays; device arrays are torch tensors on
+the current HIP device.  The solver runs on torch's current stream.
+"""
+import ctypes
+
+import numpy as np
+
+from ._lib import DGDError, FP32, FP64, BF16, c_dp, c_i8p, c_i64p, lib
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+
+def _dp(a):
+    return a.ctypes.data_as(c_dp)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Simulation:
+    """One solver instance (a ``dgd_handle``)."""
+
+    def __init__(self, N, precision="fp64", stream=None):
+        import torch
+        self._L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        st = self._L.dgd_create(int(N), prec, ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise DGDError(st, "dgd_create failed")
+        self.h = h
+        self.N = int(N)
+        self.precision = prec
+        Lm, Q, Ns, Nt = (ctypes.c_int() for _ in range(4))
+        self._chk(self._L.dgd_sizes(self.h, ctypes.byref(Lm), ctypes.byref(Q),
+                                    ctypes.byref(Ns), ctypes.byref(Nt)))
+        self.L, self.Q, self.Ns, self.Nt = Lm.value, Q.value, Ns.value, Nt.value
+        self.ne = 0
+        self.nrec = 0
+
+    def _chk(self, st):
+        if st != 0:
+            msg = self._L.dgd_last_error(self.h)
+            raise DGDError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.dgd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- setup -----------------------------------------------------------------
+    def set_mesh(self, xyz, tets, face_tag, periodic_map=None):
+        xyz = _f64(xyz)
+        tets = np.ascontiguousarray(tets, dtype=np.int64)
+        tag = np.ascontiguousarray(face_tag, dtype=np.int8)
+        pm = None if periodic_map is None else np.ascontiguousarray(periodic_map, dtype=np.int64)
+        self._chk(self._L.dgd_set_mesh(
+            self.h, xyz.shape[0], _dp(xyz), tets.shape[0], tets.ctypes.data_as(c_i64p),
+            tag.ctypes.data_as(c_i8p), None if pm is None else pm.ctypes.data_as(c_i64p)))
+        self.ne = tets.shape[0]
+
+    def set_material(self, rho, lambda0, mu0, gamma_r, xi0, Cd):
+        arrs = [_f64(a) for a in (rho, lambda0, mu0, gamma_r, xi0, Cd)]
+        self._chk(self._L.dgd_set_material(self.h, *[_dp(a) for a in arrs]))
+
+    def set_params(self, dt, alpha_max):
+        self._chk(self._L.dgd_set_params(self.h, float(dt), float(alpha_max)))
+
+    def get_quadrature_points(self):
+        out = np.zeros((self.ne, self.Q, 3))
+        self._chk(self._L.dgd_get_quadrature_points(self.h, _dp(out)))
+        return out
+
+    def set_state_from_points(self, vals):
+        v = _f64(vals, (self.ne, self.Q, 10))
+        self._chk(self._L.dgd_set_state_from_points(self.h, _dp(v)))
+
+    def set_state(self, dofs):
+        """dofs: numpy (ne, 10, L) or a float64 torch tensor on the device."""
+        if isinstance(dofs, np.ndarray):
+            d = _f64(dofs, (self.ne, 10, self.L))
+            self._chk(self._L.dgd_set_state(self.h, d.ctypes.data_as(ctypes.c_void_p), 0))
+        else:
+            assert dofs.is_cuda and dofs.is_contiguous() and dofs.numel() == self.ne * 10 * self.L
+            self._chk(self._L.dgd_set_state(self.h, ctypes.c_void_p(dofs.data_ptr()), 1))
+
+    def get_state(self, out=None):
+        if out is None:
+            out = np.zeros((self.ne, 10, self.L))
+        if isinstance(out, np.ndarray):
+            self._chk(self._L.dgd_get_state(self.h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        else:
+            self._chk(self._L.dgd_get_state(self.h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def set_time(self, t):
+        self._chk(self._L.dgd_set_time(self.h, float(t)))
+
+    def get_time(self):
+        t = ctypes.c_double()
+        self._chk(self._L.dgd_get_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    def set_point_sources(self, xyz, M6, t_onset, stf_param, stf_kind):
+        xyz = _f64(xyz, (-1, 3))
+        n = xyz.shape[0]
+        M6 = _f64(M6, (n, 6))
+        on = _f64(t_onset, (n,))
+        par = _f64(stf_param, (n,))
+        self._chk(self._L.dgd_set_point_sources(self.h, n, _dp(xyz), _dp(M6), _dp(on), _dp(par),
+                                                int(stf_kind)))
+
+    def set_receivers(self, xyz):
+        xyz = _f64(xyz, (-1, 3))
+        self._chk(self._L.dgd_set_receivers(self.h, xyz.shape[0], _dp(xyz)))
+        self.nrec = xyz.shape[0]
+
+    # ---- run ------------------------------------------------------------------------
+    def step(self, nsteps=1):
+        self._chk(self._L.dgd_step(self.h, int(nsteps)))
+
+    def set_check_interval(self, every):
+        self._chk(self._L.dgd_set_check_interval(self.h, int(every)))
+
+    def synchronize(self):
+        self._chk(self._L.dgd_synchronize(self.h))
+
+    def get_seismograms(self):
+        n = ctypes.c_int64()
+        self._chk(self._L.dgd_num_seismogram_steps(self.h, ctypes.byref(n)))
+        out = np.zeros((n.value, self.nrec, 3))
+        if n.value and self.nrec:
+            self._chk(self._L.dgd_get_seismograms(self.h, _dp(out), None))
+        return out
+
+    def clear_seismograms(self):
+        self._chk(self._L.dgd_clear_seismograms(self.h))
+
+    def energy(self):
+        e = ctypes.c_double()
+        self._chk(self._L.dgd_energy(self.h, ctypes.byref(e)))
+        return e.value
+
+    def wavespeed_change(self):
+        out = np.zeros(self.ne)
+        self._chk(self._L.dgd_wavespeed_change(self.h, _dp(out)))
+        return out
+
+    def get_time_point_states(self):
+        out = np.zeros((self.ne, self.Nt, 10, self.L))
+        self._chk(self._L.dgd_get_time_point_states(self.h, _dp(out)))
+        return out
+
+
+def from_workload(w, precision="fp64", stream=None, state=True):
+    """Simulation set up with a :class:`workloads.Workload` (mesh, material,
+    dt, initial condition projected on the device, sources, receivers)."""
+    sim = Simulation(w.N, precision, stream)
+    m = w.mesh
+    sim.set_mesh(m["xyz"], m["tets"], m["face_tag"], m["periodic_map"])
+    mat = w.material
+    sim.set_material(mat["rho"], mat["lambda0"], mat["mu0"], mat["gamma_r"], mat["xi0"], mat["Cd"])
+    sim.set_params(w.dt, w.alpha_max)
+    if state:
+        x = sim.get_quadrature_points()
+        elem = np.repeat(np.arange(sim.ne), sim.Q)
+        vals = w.ic(x.reshape(-1, 3), elem)
+        sim.set_state_from_points(vals)
+    if w.sources is not None:
+        s = w.sources
+        sim.set_point_sources(s["xyz"], s["M6"], s["t_onset"], s["stf_param"], s["stf_kind"])
+    if w.receivers is not None:
+        sim.set_receivers(w.receivers)
+    return sim

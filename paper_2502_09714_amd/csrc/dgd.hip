@@ -1,0 +1,873 @@
+// C-ABI of the MI355X ADER-DG library (see include/dgd.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dgd.h"
+#include "kernels.hpp"
+#include "refgen.hpp"
+
+using namespace dgd;
+
+namespace {
+
+struct Bf16x4 { uint16_t v[4]; };
+
+template <int P> struct HostAF;
+template <> struct HostAF<PREC_F64> { using type = double; };
+template <> struct HostAF<PREC_F32> { using type = float; };
+template <> struct HostAF<PREC_BF16> { using type = Bf16x4; };
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct dgd_handle {
+  int N = 0, prec = 0, device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  RefData ref;
+  size_t tsize = 8;  // bytes of the working type
+  // reference data on the device
+  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, PwT, wqT, Vd, wqd, Pwd;
+  double inv_wsum = 6.0, phi0_mean = 0.0;
+  // mesh and material
+  long long ne = 0;
+  bool have_mesh = false, have_mat = false, have_params = false, have_state = false;
+  std::vector<double> X0, Jm, Jinv, detJ;  // host copies for point location
+  DevBuf geo, fgeo, conn, mat;
+  std::vector<double> rho_h;
+  // state
+  DevBuf U9[2], Ua[2], Uz, flag, scratch;
+  int cur = 0;
+  double dt = 0.0, amax = 0.5, t = 0.0;
+  long long steps_since_check = 0, check_every = 64;
+  // sources and receivers
+  int nsrc = 0, srckind = 0;
+  DevBuf s_elem, s_M6, s_dphi, s_onset, s_param, s_rhoJ;
+  int nrec = 0;
+  DevBuf r_elem, r_phi, seis;
+  long long nrec_steps = 0, seis_cap = 0;
+
+  ~dgd_handle() {
+    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &PwT, &wqT, &Vd, &wqd, &Pwd, &geo, &fgeo,
+                     &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
+                     &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis};
+    for (DevBuf* b : all) b->release();
+  }
+};
+
+namespace {
+
+dgd_status fail(dgd_handle* h, dgd_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+dgd_status hip_check(dgd_handle* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return DGD_OK;
+  return fail(h, e == hipErrorOutOfMemory ? DGD_ENOMEM : DGD_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                       \
+  do {                                                        \
+    dgd_status _s = hip_check((h), (call), #call);            \
+    if (_s != DGD_OK) return _s;                              \
+  } while (0)
+
+dgd_status dalloc(dgd_handle* h, DevBuf& b, size_t bytes) {
+  if (b.n == bytes && b.p) return DGD_OK;
+  b.release();
+  if (bytes == 0) return DGD_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return hip_check(h, e, "hipMalloc");
+  }
+  b.n = bytes;
+  return DGD_OK;
+}
+
+template <class V>
+dgd_status upload(dgd_handle* h, DevBuf& b, const std::vector<V>& v) {
+  dgd_status s = dalloc(h, b, v.size() * sizeof(V));
+  if (s != DGD_OK) return s;
+  if (v.empty()) return DGD_OK;
+  HIPCHK(h, hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DGD_OK;
+}
+
+uint16_t bf16_bits(double x) { return f32_to_bf16((float)x); }
+
+// pack A (rows x cols via accessor) into fragment order [tile][kstep][lane]
+template <int P, class F>
+std::vector<typename HostAF<P>::type> pack_A(F A, int tiles, int ksteps) {
+  using AF = typename HostAF<P>::type;
+  std::vector<AF> out((size_t)tiles * ksteps * 64);
+  constexpr int KS = Prec<P>::KS;
+  for (int t = 0; t < tiles; ++t)
+    for (int s = 0; s < ksteps; ++s)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int m = 16 * t + (lane & 15);
+        AF& o = out[((size_t)t * ksteps + s) * 64 + lane];
+        if constexpr (P == PREC_BF16) {
+          for (int j = 0; j < 4; ++j) o.v[j] = bf16_bits(A(m, KS * s + 4 * (lane >> 4) + j));
+        } else {
+          o = (AF)A(m, KS * s + (lane >> 4));
+        }
+      }
+  return out;
+}
+
+template <class V>
+void append(std::vector<V>& a, const std::vector<V>& b) {
+  a.insert(a.end(), b.begin(), b.end());
+}
+
+template <int N, int P>
+dgd_status build_packed(dgd_handle* h) {
+  using DM = Dims<N>;
+  using AF = typename HostAF<P>::type;
+  using T = typename Prec<P>::T;
+  const RefData& r = h->ref;
+  constexpr int KS = Prec<P>::KS, L = DM::L, Q = DM::Q, Ns = DM::Ns;
+  constexpr int KPL = round_up(L, KS), KSL = KPL / KS, KPN = round_up(Ns, KS), KSN = KPN / KS;
+  std::vector<AF> v, k, s, f, lf;
+  for (int c = 0; c < DM::NCH; ++c)
+    append(v, pack_A<P>(
+                  [&](int m, int kk) {
+                    int q = 64 * c + m;
+                    return (q < Q && kk < L) ? r.V[(size_t)q * L + kk] : 0.0;
+                  },
+                  4, KSL));
+  k = pack_A<P>(
+      [&](int m, int kk) {
+        int e = kk / KPL, l = kk % KPL;
+        return (m < L && l < L) ? r.K[((size_t)e * L + m) * L + l] : 0.0;
+      },
+      DM::MT, 3 * KSL);
+  for (int e = 0; e < 3; ++e)
+    for (int c = 0; c < DM::NCH; ++c)
+      append(s, pack_A<P>(
+                    [&](int m, int kk) {
+                      int q = 64 * c + kk;
+                      return (m < L && q < Q) ? r.Sw[((size_t)e * L + m) * Q + q] : 0.0;
+                    },
+                    DM::MT, 64 / KS));
+  for (int ff = 0; ff < 4; ++ff)
+    for (int sp = 0; sp < 6; ++sp) {
+      const double* F = &r.F[((size_t)ff * 6 + sp) * Ns * L];
+      append(f, pack_A<P>([&](int m, int kk) { return (m < Ns && kk < L) ? F[m * L + kk] : 0.0; },
+                          DM::NST, KSL));
+      append(lf, pack_A<P>(
+                     [&](int m, int kk) {
+                       return (m < L && kk < Ns) ? r.beta[kk] * F[kk * L + m] : 0.0;
+                     },
+                     DM::MT, KSN));
+    }
+  dgd_status st;
+  if ((st = upload(h, h->Vpk, v)) || (st = upload(h, h->Kpk, k)) || (st = upload(h, h->Spk, s)) ||
+      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)))
+    return st;
+  std::vector<T> pw(r.Pw.begin(), r.Pw.end()), wq(r.wq.begin(), r.wq.end());
+  if ((st = upload(h, h->PwT, pw)) || (st = upload(h, h->wqT, wq))) return st;
+  return DGD_OK;
+}
+
+template <int N, int P>
+StepArgs<P> make_args(dgd_handle* h) {
+  using T = typename Prec<P>::T;
+  using AF = typename Prec<P>::AF;
+  StepArgs<P> a;
+  a.E = h->ne;
+  const int c = h->cur, n = 1 - h->cur;
+  a.U9 = (const T*)h->U9[c].p;
+  a.Ua = (const double*)h->Ua[c].p;
+  a.W9 = (T*)h->U9[n].p;
+  a.Wa = (double*)h->Ua[n].p;
+  a.Uz = (T*)h->Uz.p;
+  a.geo = (const double*)h->geo.p;
+  a.fgeo = (const double*)h->fgeo.p;
+  a.mat = (const double*)h->mat.p;
+  a.conn = (const int*)h->conn.p;
+  a.Vpk = (const AF*)h->Vpk.p;
+  a.Kpk = (const AF*)h->Kpk.p;
+  a.Spk = (const AF*)h->Spk.p;
+  a.Fpk = (const AF*)h->Fpk.p;
+  a.Lpk = (const AF*)h->Lpk.p;
+  a.Pw = (const T*)h->PwT.p;
+  a.wq = (const T*)h->wqT.p;
+  a.dt = h->dt;
+  a.amax = (T)h->amax;
+  a.smin = (T)1e-15;   // guard sqrt(I2) <= 1e-15, i.e. I2 <= 1e-30, in every precision
+  a.inv_wsum = (T)h->inv_wsum;
+  for (int z = 0; z < 8; ++z) {
+    a.tau[z] = z < (int)h->ref.tau.size() ? (T)h->ref.tau[z] : T(0);
+    a.gamma[z] = z < (int)h->ref.gamma.size() ? (T)h->ref.gamma[z] : T(0);
+  }
+  a.flag = (int*)h->flag.p;
+  return a;
+}
+
+template <int N, int P>
+dgd_status step_impl(dgd_handle* h, long long nsteps) {
+  using T = typename Prec<P>::T;
+  const long long per = (h->ne + 7) / 8;
+  const dim3 grid((unsigned)(8 * per)), block(64);
+  for (long long it = 0; it < nsteps; ++it) {
+    StepArgs<P> a = make_args<N, P>(h);
+    hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a);
+    hipLaunchKernelGGL((k_face_update<N, P>), grid, block, 0, h->stream, a);
+    if (h->nsrc > 0) {
+      SrcArgs s;
+      s.nsrc = h->nsrc;
+      s.L = h->ref.L;
+      s.elem = (const long long*)h->s_elem.p;
+      s.M6 = (const double*)h->s_M6.p;
+      s.dphi = (const double*)h->s_dphi.p;
+      s.onset = (const double*)h->s_onset.p;
+      s.param = (const double*)h->s_param.p;
+      s.rhoJ = (const double*)h->s_rhoJ.p;
+      s.kind = h->srckind;
+      s.t0 = h->t;
+      s.t1 = h->t + h->dt;
+      hipLaunchKernelGGL((k_sources<T>), dim3(1), dim3(3 * h->ref.L), 0, h->stream, s,
+                         (T*)h->U9[1 - h->cur].p);
+    }
+    if (h->nrec > 0) {
+      double* out = (double*)h->seis.p + (size_t)h->nrec_steps * h->nrec * 3;
+      const int nth = h->nrec * 3;
+      hipLaunchKernelGGL((k_receivers<T>), dim3((nth + 63) / 64), dim3(64), 0, h->stream, h->nrec,
+                         h->ref.L, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                         (const T*)h->U9[1 - h->cur].p, out);
+      h->nrec_steps += 1;
+    }
+    HIPCHK(h, hipGetLastError());
+    h->cur = 1 - h->cur;
+    h->t += h->dt;
+  }
+  return DGD_OK;
+}
+
+// dispatch on (N, precision)
+template <template <int, int> class Fn, class... Args>
+dgd_status dispatch(dgd_handle* h, Args... args) {
+#define DGD_CASE(NN, PP) \
+  if (h->N == NN && h->prec == PP) return Fn<NN, PP>::run(h, args...);
+  DGD_CASE(1, 0) DGD_CASE(1, 1) DGD_CASE(1, 2)
+  DGD_CASE(2, 0) DGD_CASE(2, 1) DGD_CASE(2, 2)
+  DGD_CASE(3, 0) DGD_CASE(3, 1) DGD_CASE(3, 2)
+  DGD_CASE(4, 0) DGD_CASE(4, 1) DGD_CASE(4, 2)
+#undef DGD_CASE
+  return fail(h, DGD_EINVAL, "unsupported degree/precision");
+}
+
+template <int N, int P> struct BuildFn {
+  static dgd_status run(dgd_handle* h) { return build_packed<N, P>(h); }
+};
+template <int N, int P> struct StepFn {
+  static dgd_status run(dgd_handle* h, long long n) { return step_impl<N, P>(h, n); }
+};
+
+// ---------------------------------------------------------------- mesh helpers
+const int kFV[4][3] = {{0, 2, 1}, {0, 1, 3}, {0, 3, 2}, {1, 2, 3}};
+
+bool inv3(const double* A, double* B, double* det) {
+  // A row-major 3x3
+  const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                   A[2] * (A[3] * A[7] - A[4] * A[6]);
+  *det = d;
+  if (!(d > 0.0)) return false;
+  const double id = 1.0 / d;
+  B[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+  B[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+  B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  B[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+  B[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  B[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+  B[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+  B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  return true;
+}
+
+struct FaceKey {
+  long long k[3];
+  long long ef;  // element * 4 + face
+  bool operator<(const FaceKey& o) const {
+    if (k[0] != o.k[0]) return k[0] < o.k[0];
+    if (k[1] != o.k[1]) return k[1] < o.k[1];
+    if (k[2] != o.k[2]) return k[2] < o.k[2];
+    return ef < o.ef;
+  }
+  bool same(const FaceKey& o) const { return k[0] == o.k[0] && k[1] == o.k[1] && k[2] == o.k[2]; }
+};
+
+int perm_index(const int o[3]) {
+  for (int s = 0; s < 6; ++s)
+    if (kPerm3[s][0] == o[0] && kPerm3[s][1] == o[1] && kPerm3[s][2] == o[2]) return s;
+  return -1;
+}
+
+long long locate_point(dgd_handle* h, const double* x, double xi[3]) {
+  const double tol = 1e-12;
+  for (long long e = 0; e < h->ne; ++e) {
+    const double* J = &h->Jinv[e * 9];
+    const double* o = &h->X0[e * 3];
+    double d[3] = {x[0] - o[0], x[1] - o[1], x[2] - o[2]};
+    double r[3];
+    for (int a = 0; a < 3; ++a) r[a] = J[a * 3] * d[0] + J[a * 3 + 1] * d[1] + J[a * 3 + 2] * d[2];
+    if (r[0] >= -tol && r[1] >= -tol && r[2] >= -tol && 1.0 - r[0] - r[1] - r[2] >= -tol) {
+      xi[0] = r[0];
+      xi[1] = r[1];
+      xi[2] = r[2];
+      return e;
+    }
+  }
+  return -1;
+}
+
+dgd_status ensure_seis(dgd_handle* h, long long extra) {
+  if (h->nrec == 0) return DGD_OK;
+  const long long need = h->nrec_steps + extra;
+  if (need <= h->seis_cap) return DGD_OK;
+  long long cap = std::max<long long>(need, std::max<long long>(1024, 2 * h->seis_cap));
+  void* p = nullptr;
+  HIPCHK(h, hipMalloc(&p, (size_t)cap * h->nrec * 3 * sizeof(double)));
+  if (h->seis.p && h->nrec_steps > 0)
+    HIPCHK(h, hipMemcpyAsync(p, h->seis.p, (size_t)h->nrec_steps * h->nrec * 3 * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->seis.release();
+  h->seis.p = p;
+  h->seis.n = (size_t)cap * h->nrec * 3 * sizeof(double);
+  h->seis_cap = cap;
+  return DGD_OK;
+}
+
+dgd_status alloc_state(dgd_handle* h) {
+  const size_t L = h->ref.L, E = (size_t)h->ne;
+  dgd_status s;
+  for (int i = 0; i < 2; ++i) {
+    if ((s = dalloc(h, h->U9[i], E * 9 * L * h->tsize))) return s;
+    if ((s = dalloc(h, h->Ua[i], E * L * sizeof(double)))) return s;
+  }
+  if ((s = dalloc(h, h->Uz, E * h->ref.Nt * 10 * L * h->tsize))) return s;
+  if ((s = dalloc(h, h->flag, sizeof(int)))) return s;
+  HIPCHK(h, hipMemsetAsync(h->flag.p, 0, sizeof(int), h->stream));
+  return DGD_OK;
+}
+
+template <class T>
+void launch_from_f64(dgd_handle* h, const double* src) {
+  const long long n = h->ne * 10 * h->ref.L;
+  hipLaunchKernelGGL((k_from_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                     h->ne, h->ref.L, src, (T*)h->U9[h->cur].p, (double*)h->Ua[h->cur].p);
+}
+
+template <class T>
+void launch_to_f64(dgd_handle* h, double* dst) {
+  const long long n = h->ne * 10 * h->ref.L;
+  hipLaunchKernelGGL((k_to_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                     h->ne, h->ref.L, (const T*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                     dst);
+}
+
+}  // namespace
+
+// ================================================================== C interface
+extern "C" {
+
+dgd_status dgd_create(int N, int precision, void* hip_stream, dgd_handle** out) {
+  if (!out) return DGD_EINVAL;
+  *out = nullptr;
+  if (N < 1 || N > 4 || precision < 0 || precision > 2) return DGD_EINVAL;
+  dgd_handle* h = new (std::nothrow) dgd_handle();
+  if (!h) return DGD_ENOMEM;
+  h->N = N;
+  h->prec = precision;
+  h->stream = (hipStream_t)hip_stream;
+  h->tsize = precision == DGD_FP64 ? 8 : 4;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return DGD_EDEVICE;
+  }
+  try {
+    h->ref = build_reference(N);
+  } catch (...) {
+    delete h;
+    return DGD_EINVAL;
+  }
+  double ws = 0.0;
+  for (double w : h->ref.wq) ws += w;
+  h->inv_wsum = 1.0 / ws;
+  // cell mean of phi_0 over the reference tetrahedron: 6 * int phi_0
+  double m0 = 0.0;
+  for (int q = 0; q < h->ref.Q; ++q) m0 += h->ref.wq[q] * h->ref.V[(size_t)q * h->ref.L];
+  h->phi0_mean = 6.0 * m0;
+  dgd_status s = dispatch<BuildFn>(h);
+  if (s == DGD_OK) s = upload(h, h->Vd, h->ref.V);
+  if (s == DGD_OK) s = upload(h, h->wqd, h->ref.wq);
+  if (s == DGD_OK) s = upload(h, h->Pwd, h->ref.Pw);
+  if (s != DGD_OK) {
+    delete h;
+    return s;
+  }
+  *out = h;
+  return DGD_OK;
+}
+
+dgd_status dgd_destroy(dgd_handle* h) {
+  if (h) {
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+  }
+  return DGD_OK;
+}
+
+const char* dgd_last_error(const dgd_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+dgd_status dgd_sizes(const dgd_handle* h, int* L, int* Q, int* Ns, int* Nt) {
+  if (!h) return DGD_EINVAL;
+  if (L) *L = h->ref.L;
+  if (Q) *Q = h->ref.Q;
+  if (Ns) *Ns = h->ref.Ns;
+  if (Nt) *Nt = h->ref.Nt;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_mesh(dgd_handle* h, int64_t nv, const double* xyz, int64_t ne,
+                        const int64_t* tets, const int8_t* face_tag, const int64_t* pmap) {
+  if (!h) return DGD_EINVAL;
+  if (nv <= 0 || ne <= 0 || !xyz || !tets || !face_tag) return fail(h, DGD_EINVAL, "bad mesh arguments");
+  if (ne > (1LL << 30)) return fail(h, DGD_EINVAL, "too many elements");
+  h->have_mesh = h->have_state = false;
+  std::vector<long long> ids((size_t)ne * 4);
+  for (long long i = 0; i < ne * 4; ++i) {
+    const long long v = tets[i];
+    if (v < 0 || v >= nv) return fail(h, DGD_EINVAL, "vertex id out of range");
+    long long g = v;
+    if (pmap) {
+      g = pmap[v];
+      if (g < 0 || g >= nv) return fail(h, DGD_EINVAL, "periodic map out of range");
+    }
+    ids[i] = g;
+  }
+  h->ne = ne;
+  h->X0.assign((size_t)ne * 3, 0.0);
+  h->Jinv.assign((size_t)ne * 9, 0.0);
+  h->detJ.assign((size_t)ne, 0.0);
+  std::vector<double> geo((size_t)ne * 16, 0.0), fgeo((size_t)ne * 16, 0.0);
+  for (long long e = 0; e < ne; ++e) {
+    const double* x[4];
+    for (int k = 0; k < 4; ++k) x[k] = xyz + 3 * tets[e * 4 + k];
+    double J[9];  // J[d][e] = x_{e+1,d} - x_{0,d}
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c) J[d * 3 + c] = x[c + 1][d] - x[0][d];
+    double det;
+    if (!inv3(J, &h->Jinv[e * 9], &det))
+      return fail(h, DGD_EINVAL, "inverted or degenerate tetrahedron " + std::to_string(e));
+    h->detJ[e] = det;
+    for (int d = 0; d < 3; ++d) h->X0[e * 3 + d] = x[0][d];
+    for (int k = 0; k < 9; ++k) geo[e * 16 + k] = h->Jinv[e * 9 + k];
+    geo[e * 16 + 9] = det;
+    for (int f = 0; f < 4; ++f) {
+      const double* A = x[kFV[f][0]];
+      const double* B = x[kFV[f][1]];
+      const double* C = x[kFV[f][2]];
+      double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+      double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+      double cr[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+      const double ln = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      for (int d = 0; d < 3; ++d) fgeo[(e * 4 + f) * 4 + d] = cr[d] / ln;
+      fgeo[(e * 4 + f) * 4 + 3] = 0.5 * ln / det;
+    }
+  }
+  // connectivity
+  std::vector<int> conn((size_t)ne * 8, 0);
+  std::vector<FaceKey> keys;
+  keys.reserve((size_t)ne * 4);
+  for (long long e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f) {
+      const int tag = face_tag[e * 4 + f];
+      long long g[3];
+      for (int j = 0; j < 3; ++j) g[j] = ids[e * 4 + kFV[f][j]];
+      if (g[0] == g[1] || g[0] == g[2] || g[1] == g[2])
+        return fail(h, DGD_EINVAL, "face with repeated vertices");
+      int order[3] = {0, 1, 2};
+      std::sort(order, order + 3, [&](int a, int b) { return g[a] < g[b]; });
+      const int sp = perm_index(order);
+      int kind;
+      if (tag == DGD_FACE_INTERIOR) {
+        kind = 0;
+        FaceKey k;
+        for (int j = 0; j < 3; ++j) k.k[j] = g[order[j]];
+        k.ef = e * 4 + f;
+        keys.push_back(k);
+      } else if (tag == DGD_BC_FREE) {
+        kind = 1;
+      } else if (tag == DGD_BC_ABSORB) {
+        kind = 2;
+      } else {
+        return fail(h, DGD_EINVAL, "bad face tag");
+      }
+      conn[(e * 4 + f) * 2] = -1;
+      conn[(e * 4 + f) * 2 + 1] = kind | (sp << 2);
+    }
+  std::sort(keys.begin(), keys.end());
+  for (size_t i = 0; i < keys.size();) {
+    if (i + 1 >= keys.size() || !keys[i].same(keys[i + 1]) ||
+        (i + 2 < keys.size() && keys[i].same(keys[i + 2])))
+      return fail(h, DGD_EINVAL, "interior face without exactly one partner");
+    const long long a = keys[i].ef, b = keys[i + 1].ef;
+    for (int side = 0; side < 2; ++side) {
+      const long long me = side ? b : a, ot = side ? a : b;
+      int& w = conn[(me)*2 + 1];
+      const int sq = conn_perm(conn[ot * 2 + 1]);
+      w |= ((int)(ot % 4) << 5) | (sq << 7);
+      conn[me * 2] = (int)(ot / 4);
+    }
+    i += 2;
+  }
+  dgd_status s;
+  if ((s = upload(h, h->geo, geo)) || (s = upload(h, h->fgeo, fgeo)) || (s = upload(h, h->conn, conn)))
+    return s;
+  if ((s = alloc_state(h))) return s;
+  h->have_mesh = true;
+  h->have_mat = false;
+  h->nsrc = 0;
+  h->nrec = 0;
+  h->nrec_steps = 0;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lambda0,
+                            const double* mu0, const double* gamma_r, const double* xi0,
+                            const double* Cd) {
+  if (!h) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  if (!rho || !lambda0 || !mu0 || !gamma_r || !xi0 || !Cd) return fail(h, DGD_EINVAL, "null array");
+  std::vector<double> m((size_t)h->ne * 8, 0.0);
+  h->rho_h.assign(rho, rho + h->ne);
+  for (long long e = 0; e < h->ne; ++e) {
+    if (!(rho[e] > 0.0) || !(mu0[e] > 0.0)) return fail(h, DGD_EINVAL, "rho and mu0 must be positive");
+    m[e * 8 + 0] = rho[e];
+    m[e * 8 + 1] = lambda0[e];
+    m[e * 8 + 2] = mu0[e];
+    m[e * 8 + 3] = gamma_r[e];
+    m[e * 8 + 4] = xi0[e];
+    m[e * 8 + 5] = Cd[e];
+  }
+  dgd_status s = upload(h, h->mat, m);
+  if (s) return s;
+  h->have_mat = true;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_params(dgd_handle* h, double dt, double alpha_max) {
+  if (!h) return DGD_EINVAL;
+  if (!(dt > 0.0) || !(alpha_max >= 0.0)) return fail(h, DGD_EINVAL, "dt > 0 and alpha_max >= 0 needed");
+  h->dt = dt;
+  h->amax = alpha_max;
+  h->have_params = true;
+  return DGD_OK;
+}
+
+dgd_status dgd_get_quadrature_points(dgd_handle* h, double* xyz) {
+  if (!h || !xyz) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  const int Q = h->ref.Q;
+  for (long long e = 0; e < h->ne; ++e) {
+    // x = X0 + J xi, J = inverse of Jinv (recompute from Jinv for independence of storage)
+    double J[9], det;
+    inv3(&h->Jinv[e * 9], J, &det);
+    for (int q = 0; q < Q; ++q) {
+      const double* xi = &h->ref.xq[3 * q];
+      for (int d = 0; d < 3; ++d)
+        xyz[(e * Q + q) * 3 + d] =
+            h->X0[e * 3 + d] + J[d * 3] * xi[0] + J[d * 3 + 1] * xi[1] + J[d * 3 + 2] * xi[2];
+    }
+  }
+  return DGD_OK;
+}
+
+dgd_status dgd_set_state_from_points(dgd_handle* h, const double* vals) {
+  if (!h || !vals) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  const size_t n = (size_t)h->ne * h->ref.Q * 10;
+  dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+  if (s) return s;
+  HIPCHK(h, hipMemcpyAsync(h->scratch.p, vals, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  const long long nt = h->ne * 10 * h->ref.L;
+  const dim3 g((unsigned)((nt + 255) / 256)), b(256);
+  if (h->prec == DGD_FP64)
+    hipLaunchKernelGGL((k_project<double>), g, b, 0, h->stream, h->ne, h->ref.L, h->ref.Q,
+                       (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       (double*)h->U9[h->cur].p, (double*)h->Ua[h->cur].p);
+  else
+    hipLaunchKernelGGL((k_project<float>), g, b, 0, h->stream, h->ne, h->ref.L, h->ref.Q,
+                       (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       (float*)h->U9[h->cur].p, (double*)h->Ua[h->cur].p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->scratch.release();
+  h->have_state = true;
+  h->t = 0.0;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_state(dgd_handle* h, const double* dofs, int on_device) {
+  if (!h || !dofs) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  const size_t n = (size_t)h->ne * 10 * h->ref.L;
+  const double* src = dofs;
+  if (!on_device) {
+    dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+    if (s) return s;
+    HIPCHK(h, hipMemcpyAsync(h->scratch.p, dofs, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    src = (const double*)h->scratch.p;
+  }
+  if (h->prec == DGD_FP64)
+    launch_from_f64<double>(h, src);
+  else
+    launch_from_f64<float>(h, src);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!on_device) h->scratch.release();
+  h->have_state = true;
+  h->t = 0.0;
+  return DGD_OK;
+}
+
+dgd_status dgd_get_state(dgd_handle* h, double* dofs, int on_device) {
+  if (!h || !dofs) return DGD_EINVAL;
+  if (!h->have_state) return fail(h, DGD_ESTATE, "no state");
+  const size_t n = (size_t)h->ne * 10 * h->ref.L;
+  double* dst = dofs;
+  if (!on_device) {
+    dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+    if (s) return s;
+    dst = (double*)h->scratch.p;
+  }
+  if (h->prec == DGD_FP64)
+    launch_to_f64<double>(h, dst);
+  else
+    launch_to_f64<float>(h, dst);
+  HIPCHK(h, hipGetLastError());
+  if (!on_device) {
+    HIPCHK(h, hipMemcpyAsync(dofs, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!on_device) h->scratch.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_set_time(dgd_handle* h, double t) {
+  if (!h) return DGD_EINVAL;
+  h->t = t;
+  return DGD_OK;
+}
+
+dgd_status dgd_get_time(const dgd_handle* h, double* t) {
+  if (!h || !t) return DGD_EINVAL;
+  *t = h->t;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_point_sources(dgd_handle* h, int n, const double* xyz, const double* M6,
+                                 const double* t_onset, const double* stf_param, int stf_kind) {
+  if (!h) return DGD_EINVAL;
+  if (!h->have_mesh || !h->have_mat) return fail(h, DGD_ESTATE, "mesh and material first");
+  if (n < 0 || (n > 0 && (!xyz || !M6 || !t_onset || !stf_param)))
+    return fail(h, DGD_EINVAL, "bad source arguments");
+  if (stf_kind != DGD_STF_RICKER && stf_kind != DGD_STF_GAUSSIAN)
+    return fail(h, DGD_EINVAL, "bad source time function");
+  const int L = h->ref.L;
+  std::vector<long long> elem(n);
+  std::vector<double> dphi((size_t)n * 3 * L), rhoJ(n), m6(M6, M6 + 6 * (size_t)n),
+      on(t_onset, t_onset + n), par(stf_param, stf_param + n);
+  std::vector<double> phi(L), dxi(3 * L);
+  for (int k = 0; k < n; ++k) {
+    double xi[3];
+    const long long e = locate_point(h, xyz + 3 * k, xi);
+    if (e < 0) return fail(h, DGD_EINVAL, "source outside the mesh");
+    if (!(par[k] > 0.0)) return fail(h, DGD_EINVAL, "stf parameter must be positive");
+    elem[k] = e;
+    basis_eval(h->N, xi, phi.data(), dxi.data());
+    const double* Ji = &h->Jinv[e * 9];
+    for (int d = 0; d < 3; ++d)
+      for (int l = 0; l < L; ++l) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) s += dxi[a * L + l] * Ji[a * 3 + d];
+        dphi[((size_t)k * 3 + d) * L + l] = s;
+      }
+    rhoJ[k] = h->rho_h[e] * h->detJ[e];
+  }
+  dgd_status s;
+  if ((s = upload(h, h->s_elem, elem)) || (s = upload(h, h->s_M6, m6)) ||
+      (s = upload(h, h->s_dphi, dphi)) || (s = upload(h, h->s_onset, on)) ||
+      (s = upload(h, h->s_param, par)) || (s = upload(h, h->s_rhoJ, rhoJ)))
+    return s;
+  h->nsrc = n;
+  h->srckind = stf_kind;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_receivers(dgd_handle* h, int nrec, const double* xyz) {
+  if (!h) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  if (nrec < 0 || (nrec > 0 && !xyz)) return fail(h, DGD_EINVAL, "bad receiver arguments");
+  const int L = h->ref.L;
+  std::vector<long long> elem(nrec);
+  std::vector<double> phi((size_t)nrec * L);
+  for (int r = 0; r < nrec; ++r) {
+    double xi[3];
+    const long long e = locate_point(h, xyz + 3 * r, xi);
+    if (e < 0) return fail(h, DGD_EINVAL, "receiver outside the mesh");
+    elem[r] = e;
+    basis_eval(h->N, xi, &phi[(size_t)r * L], nullptr);
+  }
+  dgd_status s;
+  if ((s = upload(h, h->r_elem, elem)) || (s = upload(h, h->r_phi, phi))) return s;
+  h->nrec = nrec;
+  h->nrec_steps = 0;
+  h->seis.release();
+  h->seis_cap = 0;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_check_interval(dgd_handle* h, int64_t every) {
+  if (!h || every < 1) return DGD_EINVAL;
+  h->check_every = every;
+  return DGD_OK;
+}
+
+dgd_status dgd_synchronize(dgd_handle* h) {
+  if (!h) return DGD_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->flag.p) {
+    int f = 0;
+    HIPCHK(h, hipMemcpy(&f, h->flag.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (f) return fail(h, DGD_ENUMERIC, "non-finite value in the state");
+  }
+  return DGD_OK;
+}
+
+dgd_status dgd_step(dgd_handle* h, int64_t nsteps) {
+  if (!h) return DGD_EINVAL;
+  if (nsteps < 0) return fail(h, DGD_EINVAL, "negative step count");
+  if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
+    return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
+  dgd_status s = ensure_seis(h, nsteps);
+  if (s) return s;
+  long long left = nsteps;
+  while (left > 0) {
+    long long chunk = std::min<long long>(left, h->check_every - h->steps_since_check);
+    if (chunk <= 0) chunk = 1;
+    if ((s = dispatch<StepFn>(h, chunk))) return s;
+    left -= chunk;
+    h->steps_since_check += chunk;
+    if (h->steps_since_check >= h->check_every) {
+      h->steps_since_check = 0;
+      if ((s = dgd_synchronize(h))) return s;
+    }
+  }
+  return DGD_OK;
+}
+
+dgd_status dgd_num_seismogram_steps(const dgd_handle* h, int64_t* n) {
+  if (!h || !n) return DGD_EINVAL;
+  *n = h->nrec_steps;
+  return DGD_OK;
+}
+
+dgd_status dgd_get_seismograms(dgd_handle* h, double* out, int64_t* nrecorded) {
+  if (!h) return DGD_EINVAL;
+  if (nrecorded) *nrecorded = h->nrec_steps;
+  if (h->nrec == 0 || h->nrec_steps == 0) return DGD_OK;
+  if (!out) return fail(h, DGD_EINVAL, "null output");
+  HIPCHK(h, hipMemcpyAsync(out, h->seis.p, (size_t)h->nrec_steps * h->nrec * 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DGD_OK;
+}
+
+dgd_status dgd_clear_seismograms(dgd_handle* h) {
+  if (!h) return DGD_EINVAL;
+  h->nrec_steps = 0;
+  return DGD_OK;
+}
+
+dgd_status dgd_energy(dgd_handle* h, double* E) {
+  if (!h || !E) return DGD_EINVAL;
+  if (!h->have_state || !h->have_mat || !h->have_params)
+    return fail(h, DGD_ESTATE, "state, material and params needed");
+  dgd_status s = dalloc(h, h->scratch, (size_t)(h->ne + 1) * sizeof(double));
+  if (s) return s;
+  double* part = (double*)h->scratch.p;
+  if (h->prec == DGD_FP64)
+    hipLaunchKernelGGL((k_energy<double>), dim3((unsigned)h->ne), dim3(64), 0, h->stream, h->ne,
+                       h->ref.L, h->ref.Q, (const double*)h->Vd.p, (const double*)h->wqd.p,
+                       (const double*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                       (const double*)h->geo.p, (const double*)h->mat.p, h->amax, 1e-15, part);
+  else
+    hipLaunchKernelGGL((k_energy<float>), dim3((unsigned)h->ne), dim3(64), 0, h->stream, h->ne,
+                       h->ref.L, h->ref.Q, (const double*)h->Vd.p, (const double*)h->wqd.p,
+                       (const float*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                       (const double*)h->geo.p, (const double*)h->mat.p, h->amax, 1e-15, part);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, h->stream, h->ne, part, part + h->ne);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(E, part + h->ne, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->scratch.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_wavespeed_change(dgd_handle* h, double* out) {
+  if (!h || !out) return DGD_EINVAL;
+  if (!h->have_state || !h->have_mat || !h->have_params)
+    return fail(h, DGD_ESTATE, "state, material and params needed");
+  dgd_status s = dalloc(h, h->scratch, (size_t)h->ne * sizeof(double));
+  if (s) return s;
+  hipLaunchKernelGGL(k_wavespeed, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->stream,
+                     h->ne, h->ref.L, (const double*)h->Ua[h->cur].p, (const double*)h->mat.p,
+                     h->amax, h->phi0_mean, (double*)h->scratch.p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, h->scratch.p, (size_t)h->ne * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->scratch.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
+  if (!h || !out) return DGD_EINVAL;
+  if (!h->have_state) return fail(h, DGD_ESTATE, "no state");
+  const size_t n = (size_t)h->ne * h->ref.Nt * 10 * h->ref.L;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->prec == DGD_FP64) {
+    HIPCHK(h, hipMemcpy(out, h->Uz.p, n * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(n);
+    HIPCHK(h, hipMemcpy(tmp.data(), h->Uz.p, n * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) out[i] = tmp[i];
+  }
+  return DGD_OK;
+}
+
+}  // extern "C"

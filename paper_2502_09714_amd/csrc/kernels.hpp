@@ -1,0 +1,553 @@
+// Per-step kernels of the ADER-DG update (gfx950).  One 64-lane wavefront owns
+// one tetrahedron; workgroups are mapped to elements so that each of the eight
+// XCDs walks a contiguous range of elements (neighbours share an L2).
+//
+// k_predict_volume  (paper Appendix A.1 and the volume/source terms of A.2)
+//   nodal values at t_n -> pointwise CDM tangent -> cell-averaged Jacobians
+//   A*_e = sum_d Theta^-1_ed Bbar^d  (Eq. CKIter-ref)
+//   D^i = -sum_e K^e D^{i-1} A*_e^T, + nodal damage source at i = 1
+//   (Eqs. CKIter-ref-matrix, CKIter-ref-source)
+//   time points U_z = sum_i (tau_z dt)^i/i! D^i  (Eq. taylor_expansion) -> HBM
+//   volume term dt sum_z gamma_z sum_e Sw^e F^e(U_z) and damage source
+//   (Eqs. 3rd term, rhs term; the nodal projection followed by the stiffness
+//   equals quadrature with Sw = w_q dphi/dxi), partial update written out.
+// k_face_update  (Appendix A.2 Eq. 2nd term, A.3)
+//   traces of both sides at the shared face points for every time point,
+//   LLF (or boundary) flux, time/space quadrature, lift, final update.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mfma.hpp"
+#include "physics.hpp"
+
+namespace dgd {
+
+template <int N> struct Dims {
+  static constexpr int L = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Q = (N + 1) * (N + 1) * (N + 1);
+  static constexpr int Ns = (N + 1) * (N + 1);
+  static constexpr int Nt = N + 1;
+  static constexpr int NCH = (Q + 63) / 64;  // 64-point chunks of volume points
+  static constexpr int MT = (L + 15) / 16;   // 16-row tiles of a mode-indexed output
+  static constexpr int NST = (Ns + 15) / 16; // 16-row tiles of a face-point output
+};
+
+// connectivity word: bits 0-1 face kind (0 interior, 1 free, 2 absorbing),
+// 2-4 own point permutation, 5-6 neighbour face, 7-9 neighbour permutation
+__host__ __device__ inline int conn_kind(int w) { return w & 3; }
+__host__ __device__ inline int conn_perm(int w) { return (w >> 2) & 7; }
+__host__ __device__ inline int conn_nface(int w) { return (w >> 5) & 3; }
+__host__ __device__ inline int conn_nperm(int w) { return (w >> 7) & 7; }
+
+template <int P> struct StepArgs {
+  using T = typename Prec<P>::T;
+  using AF = typename Prec<P>::AF;
+  long long E;
+  const T* U9;          // [E][9][L] current wave quantities
+  const double* Ua;     // [E][L] current damage (FP64)
+  T* W9;                // [E][9][L] next state
+  double* Wa;           // [E][L]
+  T* Uz;                // [E][Nt][10][L] time-point states
+  const double* geo;    // [E][16]: Theta^-1 (row e, column d), |J|
+  const double* fgeo;   // [E][4][4]: outward normal, |S_f|/|J|
+  const double* mat;    // [E][8]: rho, lambda0, mu0, gamma_r, xi0, C_d
+  const int* conn;      // [E][4][2]: neighbour, connectivity word
+  const AF* Vpk;        // volume evaluation, per 64-point chunk
+  const AF* Kpk;        // [K^0 K^1 K^2]
+  const AF* Spk;        // Sw^e per chunk
+  const AF* Fpk;        // face traces [f][perm]
+  const AF* Lpk;        // lift [f][perm]
+  const T* Pw;          // [L][Q]
+  const T* wq;          // [Q]
+  double dt;
+  T amax, smin, inv_wsum;
+  T tau[8], gamma[8];
+  int* flag;
+};
+
+__device__ inline long long elem_of_block(long long E) {
+  const long long per = (E + 7) / 8;
+  const long long b = blockIdx.x;
+  return (b % 8) * per + b / 8;
+}
+
+template <class T>
+__device__ inline MatP<T> load_mat(const double* p) {
+  MatP<T> m;
+  m.rho = (T)p[0];
+  m.lam = (T)p[1];
+  m.mu = (T)p[2];
+  m.gr = (T)p[3];
+  m.xi0 = (T)p[4];
+  m.cd = (T)p[5];
+  return m;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
+__device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  __shared__ T sD[N + 1][KPL * 16];
+  __shared__ T sY[3 * KPL * 16];
+  __shared__ T sW[KPL * 16];
+  __shared__ T sX[64 * 16];
+  __shared__ T sA[300];
+  __shared__ T sR[NCH * 64];
+  __shared__ T sAcc[42];
+  __shared__ T sJ[9];
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+
+  for (int i = lane; i < (N + 1) * KPL * 16; i += 64) (&sD[0][0])[i] = T(0);
+  for (int i = lane; i < 3 * KPL * 16; i += 64) sY[i] = T(0);
+  for (int i = lane; i < KPL * 16; i += 64) sW[i] = T(0);
+  __syncthreads();
+  const T* U9 = a.U9 + e * 9 * L;
+  for (int i = lane; i < 10 * L; i += 64) {
+    const int p = i / L, l = i % L;
+    sD[0][l * 16 + p] = p < 9 ? U9[p * L + l] : (T)a.Ua[e * L + l];
+  }
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = (T)a.geo[e * 16 + k];
+  __syncthreads();
+
+  // 1. cell average of the pointwise tangent and nodal damage rate at t_n
+  T acc[42];
+#pragma unroll
+  for (int k = 0; k < 42; ++k) acc[k] = T(0);
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    Acc C[4];
+    zero_C<P, 4>(C);
+    wave_gemm<P, 4>(a.Vpk + (size_t)c * 4 * KSL * 64, KSL, sD[0], C, lane);
+    store_C<P, 4>(C, sX, 64, T(1), lane);
+    __syncthreads();
+    const int q = 64 * c + lane;
+    if (q < Q) {
+      T u[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+      T ds[6][7];
+      cdm_tangent(u, m, law, ds);
+      const T w = a.wq[q];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc[k * 7 + j] += w * ds[k][j];
+      sR[q] = cdm_rate(u, m, law);
+    } else {
+      sR[q] = T(0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 42; ++k) {
+    const T v = wave_sum(acc[k]) * a.inv_wsum;
+    if (lane == 0) sAcc[k] = v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sJ[k] = Ji[k];
+  }
+  __syncthreads();
+
+  // 2. A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each)
+  for (int i = lane; i < 300; i += 64) {
+    const int ee = i / 100, p = (i / 10) % 10, q = i % 10;
+    T v = T(0);
+    if (p < 6 && q >= 6 && q < 9) {
+      const int mm = q - 6, ii = kVI[p], jj = kVJ[p];
+      v = T(-0.5) * ((ii == mm ? sJ[ee * 3 + jj] : T(0)) + (jj == mm ? sJ[ee * 3 + ii] : T(0)));
+    } else if (p >= 6 && p < 9 && (q < 6 || q == 9)) {
+      const int ii = p - 6, col = q < 6 ? q : 6;
+      T s = T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s += sJ[ee * 3 + d] * sAcc[sym_idx(ii, d) * 7 + col];
+      v = -s / m.rho;
+    }
+    sA[i] = v;
+  }
+  T src = T(0);
+  if (lane < L)
+    for (int q = 0; q < Q; ++q) src += a.Pw[lane * Q + q] * sR[q];
+  __syncthreads();
+
+  // 3. Cauchy-Kovalevskaya recursion
+#pragma unroll
+  for (int i = 1; i <= N; ++i) {
+    for (int idx = lane; idx < 3 * L * 10; idx += 64) {
+      const int ee = idx / (L * 10), l = (idx / 10) % L, p = idx % 10;
+      const T* Ar = sA + ee * 100 + p * 10;
+      const T* Dr = &sD[i - 1][l * 16];
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) s += Dr[q] * Ar[q];
+      sY[(ee * KPL + l) * 16 + p] = s;
+    }
+    __syncthreads();
+    Acc C[MT];
+    zero_C<P, MT>(C);
+    wave_gemm<P, MT>(a.Kpk, 3 * KSL, sY, C, lane);
+    store_C<P, MT>(C, sD[i], L, T(-1), lane);
+    __syncthreads();
+    if (i == 1 && lane < L) sD[1][lane * 16 + 9] += src;
+    __syncthreads();
+  }
+
+  // 4. time points and volume integrands
+  T gacc[NCH][27];
+  T sacc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    sacc[c] = T(0);
+#pragma unroll
+    for (int k = 0; k < 27; ++k) gacc[c][k] = T(0);
+  }
+  T* Uzo = a.Uz + (size_t)e * Nt * 10 * L;
+  const T ir = T(1) / m.rho;
+  for (int z = 0; z < Nt; ++z) {
+    T cz[N + 1];
+    cz[0] = T(1);
+    const T h = a.tau[z] * (T)a.dt;
+#pragma unroll
+    for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+    for (int idx = lane; idx < 10 * L; idx += 64) {
+      const int p = idx / L, l = idx % L;
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][l * 16 + p];
+      sW[l * 16 + p] = v;
+      Uzo[(z * 10 + p) * L + l] = v;
+    }
+    __syncthreads();
+    const T g = a.gamma[z];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      Acc C[4];
+      zero_C<P, 4>(C);
+      wave_gemm<P, 4>(a.Vpk + (size_t)c * 4 * KSL * 64, KSL, sW, C, lane);
+      store_C<P, 4>(C, sX, 64, T(1), lane);
+      __syncthreads();
+      const int q = 64 * c + lane;
+      if (q < Q) {
+        T u[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+        T sig[6];
+        cdm_stress(u, m, law, sig);
+        sacc[c] += g * cdm_rate(u, m, law);
+        const T* v = u + 6;
+#pragma unroll
+        for (int ee = 0; ee < 3; ++ee) {
+          const T* Jr = Ji + ee * 3;
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+            const int ii = kVI[p], jj = kVJ[p];
+            gacc[c][ee * 9 + p] += g * (T(-0.5) * (Jr[jj] * v[ii] + Jr[ii] * v[jj]));
+          }
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) {
+            T s = T(0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s += Jr[d] * sig[sym_idx(ii, d)];
+            gacc[c][ee * 9 + 6 + ii] += g * (-ir * s);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // 5. volume contraction  Vol = sum_e Sw^e G^e
+  Acc Vc[MT];
+  zero_C<P, MT>(Vc);
+#pragma unroll
+  for (int ee = 0; ee < 3; ++ee) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) sX[lane * 16 + p] = p < 9 ? gacc[c][ee * 9 + p] : T(0);
+      __syncthreads();
+      wave_gemm<P, MT>(a.Spk + (size_t)(ee * NCH + c) * MT * (64 / KS) * 64, 64 / KS, sX, Vc, lane);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) sR[64 * c + lane] = sacc[c];
+  __syncthreads();
+  T srcv = T(0);
+  if (lane < L)
+    for (int q = 0; q < Q; ++q) srcv += a.Pw[lane * Q + q] * sR[q];
+  store_C<P, MT>(Vc, sW, L, (T)a.dt, lane);
+  __syncthreads();
+  T* W9 = a.W9 + e * 9 * L;
+  for (int idx = lane; idx < 9 * L; idx += 64) {
+    const int p = idx / L, l = idx % L;
+    W9[idx] = sD[0][l * 16 + p] + sW[l * 16 + p];
+  }
+  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * srcv);
+}
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
+  constexpr int TS = NST * 16 * 16;
+  static_assert(Nt * TS >= MT * 16 * 16, "scratch too small");
+  __shared__ T sTm[Nt * TS];
+  __shared__ T sTp[Nt * TS];
+  __shared__ T sF[KPN * 16];
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  for (int i = lane; i < KPN * 16; i += 64) sF[i] = T(0);
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  const T* Uze = a.Uz + (size_t)e * Nt * 10 * L;
+  Acc Fc[MT];
+  zero_C<P, MT>(Fc);
+  __syncthreads();
+
+  for (int f = 0; f < 4; ++f) {
+    const int nb = a.conn[(e * 4 + f) * 2];
+    const int w = a.conn[(e * 4 + f) * 2 + 1];
+    const int kind = conn_kind(w), sp = conn_perm(w);
+    for (int z = 0; z < Nt; ++z) {
+      Acc C[NST];
+      zero_C<P, NST>(C);
+      wave_gemm_g<P, NST>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, KSL, Uze + z * 10 * L, L,
+                          L, C, lane);
+      store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+    }
+    if (kind == 0) {
+      const int nf = conn_nface(w), sq = conn_nperm(w);
+      const T* Uzn = a.Uz + (size_t)nb * Nt * 10 * L;
+      for (int z = 0; z < Nt; ++z) {
+        Acc C[NST];
+        zero_C<P, NST>(C);
+        wave_gemm_g<P, NST>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64, KSL,
+                            Uzn + z * 10 * L, L, L, C, lane);
+        store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
+      }
+    }
+    __syncthreads();
+    T n[3];
+    n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
+    n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
+    n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
+    const T fsc = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
+    const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
+    for (int idx = lane; idx < Ns * Nt; idx += 64) {
+      const int i = idx % Ns, z = idx / Ns;
+      T* um = sTm + z * TS + i * 16;
+      T uM[10], F[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) uM[k] = um[k];
+      if (kind == 0) {
+        T uP[10];
+        const T* up = sTp + z * TS + i * 16;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) uP[k] = up[k];
+        llf_flux(uM, uP, n, m, mp, law, F);
+      } else {
+        boundary_flux(kind, uM, n, m, law, F);
+      }
+      const T g = a.gamma[z] * fsc;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) um[k] = g * F[k];
+    }
+    __syncthreads();
+    for (int idx = lane; idx < Ns * 10; idx += 64) {
+      const int i = idx / 10, p = idx % 10;
+      T s = T(0);
+#pragma unroll
+      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + i * 16 + p];
+      sF[i * 16 + p] = s;
+    }
+    __syncthreads();
+    wave_gemm<P, MT>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, KSN, sF, Fc, lane);
+    __syncthreads();
+  }
+  store_C<P, MT>(Fc, sTm, L, T(1), lane);
+  __syncthreads();
+  T* W9 = a.W9 + e * 9 * L;
+  bool bad = false;
+  for (int idx = lane; idx < 9 * L; idx += 64) {
+    const int p = idx / L, l = idx % L;
+    const T v = W9[idx] - sTm[l * 16 + p];
+    bad |= !isfinite(v);
+    W9[idx] = v;
+  }
+  if (lane < L) {
+    const double v = a.Wa[e * L + lane] - (double)sTm[lane * 16 + 9];
+    bad |= !isfinite(v);
+    a.Wa[e * L + lane] = v;
+  }
+  if (bad) a.flag[0] = 1;
+}
+
+// ---- point sources, receivers, projection, diagnostics ------------------------
+
+__device__ inline double stf_G(int kind, double tau, double p) {
+  if (kind == 0) {
+    const double aa = (M_PI * p) * (M_PI * p);
+    return -exp(-aa * tau * tau) / (2.0 * aa);
+  }
+  return 0.5 * (tau * (1.0 + erf(tau / p)) + p * exp(-tau * tau / (p * p)) / sqrt(M_PI));
+}
+
+struct SrcArgs {
+  int nsrc, L;
+  const long long* elem;   // [nsrc]
+  const double* M6;        // [nsrc][6]
+  const double* dphi;      // [nsrc][3][L]  dphi_l/dx_d at the source
+  const double* onset;     // [nsrc]
+  const double* param;     // [nsrc]
+  const double* rhoJ;      // [nsrc]  rho |J| of the host element
+  int kind;
+  double t0, t1;
+};
+
+template <class T>
+__global__ void k_sources(SrcArgs s, T* U9) {
+  const int idx = threadIdx.x;   // (i, l)
+  if (idx >= 3 * s.L) return;
+  const int i = idx / s.L, l = idx % s.L;
+  for (int k = 0; k < s.nsrc; ++k) {
+    const double dG = stf_G(s.kind, s.t1 - s.onset[k], s.param[k]) -
+                      stf_G(s.kind, s.t0 - s.onset[k], s.param[k]);
+    const double fac = dG / s.rhoJ[k];
+    double v = 0.0;
+    for (int j = 0; j < 3; ++j) v += s.M6[k * 6 + sym_idx(i, j)] * s.dphi[(k * 3 + j) * s.L + l];
+    T* dst = U9 + (s.elem[k] * 9 + 6 + i) * s.L + l;
+    *dst = (T)((double)*dst + fac * v);
+  }
+}
+
+template <class T>
+__global__ void k_receivers(int nrec, int L, const long long* elem, const double* phi,
+                            const T* U9, double* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nrec * 3) return;
+  const int r = idx / 3, c = idx % 3;
+  const T* u = U9 + (elem[r] * 9 + 6 + c) * L;
+  double s = 0.0;
+  for (int l = 0; l < L; ++l) s += phi[r * L + l] * (double)u[l];
+  out[idx] = s;
+}
+
+// L2 projection of point values [E][Q][10] onto the modes (FP64)
+template <class T>
+__global__ void k_project(long long E, int L, int Q, const double* Pw, const double* vals, T* U9,
+                          double* Ua) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * 10 * L) return;
+  const long long e = idx / (10 * L);
+  const int p = (int)((idx / L) % 10), l = (int)(idx % L);
+  double s = 0.0;
+  for (int q = 0; q < Q; ++q) s += Pw[l * Q + q] * vals[(e * Q + q) * 10 + p];
+  if (p < 9)
+    U9[(e * 9 + p) * L + l] = (T)s;
+  else
+    Ua[e * L + l] = s;
+}
+
+template <class T>
+__global__ void k_to_f64(long long E, int L, const T* U9, const double* Ua, double* out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * 10 * L) return;
+  const long long e = idx / (10 * L);
+  const int p = (int)((idx / L) % 10), l = (int)(idx % L);
+  out[idx] = p < 9 ? (double)U9[(e * 9 + p) * L + l] : Ua[e * L + l];
+}
+
+template <class T>
+__global__ void k_from_f64(long long E, int L, const double* in, T* U9, double* Ua) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * 10 * L) return;
+  const long long e = idx / (10 * L);
+  const int p = (int)((idx / L) % 10), l = (int)(idx % L);
+  if (p < 9)
+    U9[(e * 9 + p) * L + l] = (T)in[idx];
+  else
+    Ua[e * L + l] = in[idx];
+}
+
+// energy: one wave per element, lanes over volume points (FP64)
+template <class T>
+__global__ __launch_bounds__(64) void k_energy(long long E, int L, int Q, const double* V,
+                                               const double* wq, const T* U9, const double* Ua,
+                                               const double* geo, const double* mat, double amax,
+                                               double smin, double* part) {
+  const long long e = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (e >= E) return;
+  const MatP<double> m = load_mat<double>(mat + e * 8);
+  const Law<double> law{amax, smin};
+  double acc = 0.0;
+  for (int q = lane; q < Q; q += 64) {
+    double u[10];
+    for (int p = 0; p < 10; ++p) {
+      double s = 0.0;
+      for (int l = 0; l < L; ++l)
+        s += V[q * L + l] * (p < 9 ? (double)U9[(e * 9 + p) * L + l] : Ua[e * L + l]);
+      u[p] = s;
+    }
+    const double kin = 0.5 * m.rho * (u[6] * u[6] + u[7] * u[7] + u[8] * u[8]);
+    acc += wq[q] * (kin + cdm_energy(u, m, law));
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) part[e] = acc * geo[e * 16 + 9];
+}
+
+__global__ void k_reduce_sum(long long n, const double* in, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) s += in[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void k_wavespeed(long long E, int L, const double* Ua, const double* mat, double amax,
+                            double phi0_mean, double* out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double ab = phi0_mean * Ua[e * L];
+  ab = ab < 0.0 ? 0.0 : (ab > amax ? amax : ab);
+  const double mu = mat[e * 8 + 2];
+  double md = mu + ab * mat[e * 8 + 4] * mat[e * 8 + 3];
+  md = md > 0.0 ? md : 0.0;
+  out[e] = sqrt(md / mu) - 1.0;
+}
+
+}  // namespace dgd

@@ -1,0 +1,154 @@
+// Wave-level matrix-core helpers for gfx950 (CDNA4), one 64-lane wavefront.
+//
+// Every reference-matrix contraction of the step is C(M x 16) += A(M x K) B(K x 16)
+// with A a reference matrix (shared by all elements, pre-packed on the host in
+// fragment order so that one fragment is one coalesced load) and B a
+// per-element matrix with the 10 conservative variables in its 16 columns.
+// Fragment layout of the 16x16xK instructions (lane l, 0..63):
+//   A: row l%16, k = KS*s + (KS/4)*(l/16) + j      (j < KS/4)
+//   B: col l%16, same k
+//   C: col l%16, rows 4*(l/16) + i (FP32 accumulators) or (l/16) + 4*i
+//      (FP64 accumulators)                                          (i < 4)
+// KS = 4 for FP64 / FP32 (v_mfma_*_16x16x4), KS = 16 for BF16 inputs
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgd {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+__host__ __device__ inline uint16_t f32_to_bf16(float x) {
+  // round to nearest even (inputs are finite)
+  union { float f; uint32_t u; } v;
+  v.f = x;
+  uint32_t lsb = (v.u >> 16) & 1u;
+  v.u += 0x7fffu + lsb;
+  return (uint16_t)(v.u >> 16);
+}
+
+template <int P> struct Prec;
+
+template <> struct Prec<PREC_F64> {
+  using T = double;
+  using Acc = f64x4;
+  using AF = double;
+  static constexpr int KS = 4;
+  __device__ static inline int crow(int lane, int i) { return (lane >> 4) + 4 * i; }
+  __device__ static inline Acc mma(AF a, AF b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // B fragment from a [K][16] row-major LDS matrix
+  __device__ static inline AF loadB(const T* B, int s, int lane) {
+    return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
+  }
+  // B fragment straight from global memory: B[k][n] = g[n * ld + k] for n < 10, k < kmax
+  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
+    int n = lane & 15, k = KS * s + (lane >> 4);
+    return (n < 10 && k < kmax) ? g[n * ld + k] : 0.0;
+  }
+};
+
+template <> struct Prec<PREC_F32> {
+  using T = float;
+  using Acc = f32x4;
+  using AF = float;
+  static constexpr int KS = 4;
+  __device__ static inline int crow(int lane, int i) { return 4 * (lane >> 4) + i; }
+  __device__ static inline Acc mma(AF a, AF b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline AF loadB(const T* B, int s, int lane) {
+    return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
+  }
+  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
+    int n = lane & 15, k = KS * s + (lane >> 4);
+    return (n < 10 && k < kmax) ? g[n * ld + k] : 0.0f;
+  }
+};
+
+template <> struct Prec<PREC_BF16> {
+  using T = float;
+  using Acc = f32x4;
+  using AF = bf16x4;
+  static constexpr int KS = 16;
+  __device__ static inline int crow(int lane, int i) { return 4 * (lane >> 4) + i; }
+  __device__ static inline Acc mma(AF a, AF b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline AF loadB(const T* B, int s, int lane) {
+    int k0 = KS * s + 4 * (lane >> 4), n = lane & 15;
+    AF r;
+    r[0] = (short)f32_to_bf16(B[(k0 + 0) * 16 + n]);
+    r[1] = (short)f32_to_bf16(B[(k0 + 1) * 16 + n]);
+    r[2] = (short)f32_to_bf16(B[(k0 + 2) * 16 + n]);
+    r[3] = (short)f32_to_bf16(B[(k0 + 3) * 16 + n]);
+    return r;
+  }
+  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
+    int n = lane & 15, k0 = KS * s + 4 * (lane >> 4);
+    AF r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = (n < 10 && k0 + j < kmax) ? g[n * ld + k0 + j] : 0.0f;
+      r[j] = (short)f32_to_bf16(v);
+    }
+    return r;
+  }
+};
+
+__host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane]
+template <int P, int MT>
+__device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk, int ksteps,
+                                 const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT],
+                                 int lane) {
+  using PR = Prec<P>;
+  for (int s = 0; s < ksteps; ++s) {
+    typename PR::AF b = PR::loadB(B, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * ksteps + s) * 64 + lane], b, C[t]);
+  }
+}
+
+// Same with B read from global memory (per-element state [10][ld])
+template <int P, int MT>
+__device__ inline void wave_gemm_g(const typename Prec<P>::AF* __restrict__ Apk, int ksteps,
+                                   const typename Prec<P>::T* __restrict__ g, int ld, int kmax,
+                                   typename Prec<P>::Acc (&C)[MT], int lane) {
+  using PR = Prec<P>;
+  for (int s = 0; s < ksteps; ++s) {
+    typename PR::AF b = PR::loadBg(g, ld, kmax, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * ksteps + s) * 64 + lane], b, C[t]);
+  }
+}
+
+// Store C tiles to a [rows][16] LDS matrix, rows >= rmax dropped, times scale.
+template <int P, int MT>
+__device__ inline void store_C(const typename Prec<P>::Acc (&C)[MT], typename Prec<P>::T* dst,
+                               int rmax, typename Prec<P>::T scale, int lane) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int r = 16 * t + Prec<P>::crow(lane, i);
+      if (r < rmax) dst[r * 16 + (lane & 15)] = scale * C[t][i];
+    }
+}
+
+template <int P, int MT>
+__device__ inline void zero_C(typename Prec<P>::Acc (&C)[MT]) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[t][i] = 0;
+}
+
+}  // namespace dgd
