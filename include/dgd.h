@@ -101,13 +101,15 @@ dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lamb
  * alpha wherever it is used (the stored alpha is never modified). */
 dgd_status dgd_set_params(dgd_handle* h, double dt, double alpha_max);
 
-/* Physical coordinates of every volume quadrature point, host array
- * [ne][Q][3].  Needs the mesh. */
-dgd_status dgd_get_quadrature_points(dgd_handle* h, double* xyz);
+/* Physical coordinates of the volume quadrature points of elements
+ * [e0, e0+count), host array [count][Q][3].  Needs the mesh. */
+dgd_status dgd_get_quadrature_points(dgd_handle* h, int64_t e0, int64_t count, double* xyz);
 
-/* L2 projection onto the modes of point values vals [ne][Q][10] (host),
- * done on the device.  Sets the state and resets the time to 0. */
-dgd_status dgd_set_state_from_points(dgd_handle* h, const double* vals);
+/* L2 projection onto the modes of point values vals [count][Q][10] (host)
+ * for elements [e0, e0+count), done on the device (large meshes are filled
+ * in slices).  Marks the state as set and resets the time to 0. */
+dgd_status dgd_set_state_from_points(dgd_handle* h, int64_t e0, int64_t count,
+                                     const double* vals);
 
 /* Modal state [ne][10][L] FP64, host (on_device = 0) or device memory.
  * set_state resets the time to 0 unless dgd_set_time is called after it. */
@@ -153,6 +155,14 @@ dgd_status dgd_clear_seismograms(dgd_handle* h);
  * alpha).  Both synchronise. */
 dgd_status dgd_energy(dgd_handle* h, double* E);
 dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
+
+/* Per-kernel timing with HIP events recorded on the solver's stream around
+ * every launch while profiling is on.  dgd_get_kernel_times synchronises,
+ * returns the summed milliseconds and launch counts of the kernels
+ * {0: predictor + volume, 1: faces + update, 2: sources, 3: receivers}
+ * since the last call, and resets them. */
+dgd_status dgd_set_profiling(dgd_handle* h, int on);
+dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms /* 4 */, int64_t* launches /* 4 */);
 
 /* Intermediate results of the last dgd_step call for testing: the time-point
  * states U(t_n + tau_z dt) of its last step, [ne][Nt][10][L] FP64 host.

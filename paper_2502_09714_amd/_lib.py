@@ -31,8 +31,8 @@ _SIGS = {
     "dgd_set_mesh": (ctypes.c_int, [H, ctypes.c_int64, c_dp, ctypes.c_int64, c_i64p, c_i8p, c_i64p]),
     "dgd_set_material": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp, c_dp, c_dp]),
     "dgd_set_params": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double]),
-    "dgd_get_quadrature_points": (ctypes.c_int, [H, c_dp]),
-    "dgd_set_state_from_points": (ctypes.c_int, [H, c_dp]),
+    "dgd_get_quadrature_points": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, c_dp]),
+    "dgd_set_state_from_points": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, c_dp]),
     "dgd_set_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int]),
     "dgd_get_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int]),
     "dgd_set_time": (ctypes.c_int, [H, ctypes.c_double]),
@@ -48,6 +48,8 @@ _SIGS = {
     "dgd_energy": (ctypes.c_int, [H, c_dp]),
     "dgd_wavespeed_change": (ctypes.c_int, [H, c_dp]),
     "dgd_get_time_point_states": (ctypes.c_int, [H, c_dp]),
+    "dgd_set_profiling": (ctypes.c_int, [H, ctypes.c_int]),
+    "dgd_get_kernel_times": (ctypes.c_int, [H, c_dp, c_i64p]),
 }
 
 

@@ -80,14 +80,17 @@ class Simulation:
     def set_params(self, dt, alpha_max):
         self._chk(self._L.dgd_set_params(self.h, float(dt), float(alpha_max)))
 
-    def get_quadrature_points(self):
-        out = np.zeros((self.ne, self.Q, 3))
-        self._chk(self._L.dgd_get_quadrature_points(self.h, _dp(out)))
+    def get_quadrature_points(self, e0=0, count=None):
+        count = self.ne - e0 if count is None else count
+        out = np.zeros((count, self.Q, 3))
+        self._chk(self._L.dgd_get_quadrature_points(self.h, int(e0), int(count), _dp(out)))
         return out
 
-    def set_state_from_points(self, vals):
-        v = _f64(vals, (self.ne, self.Q, 10))
-        self._chk(self._L.dgd_set_state_from_points(self.h, _dp(v)))
+    def set_state_from_points(self, vals, e0=0):
+        v = _f64(vals)
+        count = v.size // (self.Q * 10)
+        v = v.reshape(count, self.Q, 10)
+        self._chk(self._L.dgd_set_state_from_points(self.h, int(e0), int(count), _dp(v)))
 
     def set_state(self, dofs):
         """dofs: numpy (ne, 10, L) or a float64 torch tensor on the device."""
@@ -160,6 +163,16 @@ class Simulation:
         self._chk(self._L.dgd_wavespeed_change(self.h, _dp(out)))
         return out
 
+    def set_profiling(self, on=True):
+        self._chk(self._L.dgd_set_profiling(self.h, int(bool(on))))
+
+    def get_kernel_times(self):
+        """(ms[4], launches[4]) for predictor+volume, faces+update, sources, receivers."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        self._chk(self._L.dgd_get_kernel_times(self.h, _dp(ms), n.ctypes.data_as(c_i64p)))
+        return ms, n
+
     def get_time_point_states(self):
         out = np.zeros((self.ne, self.Nt, 10, self.L))
         self._chk(self._L.dgd_get_time_point_states(self.h, _dp(out)))
@@ -176,10 +189,13 @@ def from_workload(w, precision="fp64", stream=None, state=True):
     sim.set_material(mat["rho"], mat["lambda0"], mat["mu0"], mat["gamma_r"], mat["xi0"], mat["Cd"])
     sim.set_params(w.dt, w.alpha_max)
     if state:
-        x = sim.get_quadrature_points()
-        elem = np.repeat(np.arange(sim.ne), sim.Q)
-        vals = w.ic(x.reshape(-1, 3), elem)
-        sim.set_state_from_points(vals)
+        # evaluate the initial condition slice by slice to bound host memory
+        chunk = max(1, (1 << 22) // sim.Q)
+        for e0 in range(0, sim.ne, chunk):
+            cnt = min(chunk, sim.ne - e0)
+            x = sim.get_quadrature_points(e0, cnt)
+            elem = np.repeat(np.arange(e0, e0 + cnt), sim.Q)
+            sim.set_state_from_points(w.ic(x.reshape(-1, 3), elem), e0)
     if w.sources is not None:
         s = w.sources
         sim.set_point_sources(s["xyz"], s["M6"], s["t_onset"], s["stf_param"], s["stf_kind"])

@@ -61,12 +61,21 @@ struct dgd_handle {
   int nrec = 0;
   DevBuf r_elem, r_phi, seis;
   long long nrec_steps = 0, seis_cap = 0;
+  // profiling: event pairs per kernel class
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 
   ~dgd_handle() {
     DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &PwT, &wqT, &Vd, &wqd, &Pwd, &geo, &fgeo,
                      &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis};
     for (DevBuf* b : all) b->release();
+    for (auto& u : ev_used) {
+      (void)hipEventDestroy(u.second.first);
+      (void)hipEventDestroy(u.second.second);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -189,6 +198,35 @@ dgd_status build_packed(dgd_handle* h) {
   return DGD_OK;
 }
 
+hipEvent_t take_event(dgd_handle* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// record an event pair around the launch of kernel class k when profiling
+template <class F>
+void timed(dgd_handle* h, int k, F launch) {
+  if (!h->profiling) {
+    launch();
+    return;
+  }
+  hipEvent_t a = take_event(h), b = take_event(h);
+  if (!a || !b) {
+    launch();
+    return;
+  }
+  (void)hipEventRecord(a, h->stream);
+  launch();
+  (void)hipEventRecord(b, h->stream);
+  h->ev_used.push_back({k, {a, b}});
+}
+
 template <int N, int P>
 StepArgs<P> make_args(dgd_handle* h) {
   using T = typename Prec<P>::T;
@@ -231,8 +269,8 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
   const dim3 grid((unsigned)(8 * per)), block(64);
   for (long long it = 0; it < nsteps; ++it) {
     StepArgs<P> a = make_args<N, P>(h);
-    hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a);
-    hipLaunchKernelGGL((k_face_update<N, P>), grid, block, 0, h->stream, a);
+    timed(h, 0, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
+    timed(h, 1, [&] { hipLaunchKernelGGL((k_face_update<N, P>), grid, block, 0, h->stream, a); });
     if (h->nsrc > 0) {
       SrcArgs s;
       s.nsrc = h->nsrc;
@@ -246,15 +284,19 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
       s.kind = h->srckind;
       s.t0 = h->t;
       s.t1 = h->t + h->dt;
-      hipLaunchKernelGGL((k_sources<T>), dim3(1), dim3(3 * h->ref.L), 0, h->stream, s,
-                         (T*)h->U9[1 - h->cur].p);
+      timed(h, 2, [&] {
+        hipLaunchKernelGGL((k_sources<T>), dim3(1), dim3(3 * h->ref.L), 0, h->stream, s,
+                           (T*)h->U9[1 - h->cur].p);
+      });
     }
     if (h->nrec > 0) {
       double* out = (double*)h->seis.p + (size_t)h->nrec_steps * h->nrec * 3;
       const int nth = h->nrec * 3;
-      hipLaunchKernelGGL((k_receivers<T>), dim3((nth + 63) / 64), dim3(64), 0, h->stream, h->nrec,
-                         h->ref.L, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
-                         (const T*)h->U9[1 - h->cur].p, out);
+      timed(h, 3, [&] {
+        hipLaunchKernelGGL((k_receivers<T>), dim3((nth + 63) / 64), dim3(64), 0, h->stream,
+                           h->nrec, h->ref.L, (const long long*)h->r_elem.p,
+                           (const double*)h->r_phi.p, (const T*)h->U9[1 - h->cur].p, out);
+      });
       h->nrec_steps += 1;
     }
     HIPCHK(h, hipGetLastError());
@@ -588,11 +630,13 @@ dgd_status dgd_set_params(dgd_handle* h, double dt, double alpha_max) {
   return DGD_OK;
 }
 
-dgd_status dgd_get_quadrature_points(dgd_handle* h, double* xyz) {
+dgd_status dgd_get_quadrature_points(dgd_handle* h, int64_t e0, int64_t count, double* xyz) {
   if (!h || !xyz) return DGD_EINVAL;
   if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  if (e0 < 0 || count < 0 || e0 + count > h->ne) return fail(h, DGD_EINVAL, "element range");
   const int Q = h->ref.Q;
-  for (long long e = 0; e < h->ne; ++e) {
+  xyz -= (size_t)e0 * Q * 3;
+  for (long long e = e0; e < e0 + count; ++e) {
     // x = X0 + J xi, J = inverse of Jinv (recompute from Jinv for independence of storage)
     double J[9], det;
     inv3(&h->Jinv[e * 9], J, &det);
@@ -606,23 +650,28 @@ dgd_status dgd_get_quadrature_points(dgd_handle* h, double* xyz) {
   return DGD_OK;
 }
 
-dgd_status dgd_set_state_from_points(dgd_handle* h, const double* vals) {
+dgd_status dgd_set_state_from_points(dgd_handle* h, int64_t e0, int64_t count,
+                                     const double* vals) {
   if (!h || !vals) return DGD_EINVAL;
   if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
-  const size_t n = (size_t)h->ne * h->ref.Q * 10;
+  if (e0 < 0 || count <= 0 || e0 + count > h->ne) return fail(h, DGD_EINVAL, "element range");
+  const size_t n = (size_t)count * h->ref.Q * 10;
   dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
   if (s) return s;
   HIPCHK(h, hipMemcpyAsync(h->scratch.p, vals, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  const long long nt = h->ne * 10 * h->ref.L;
+  const long long nt = count * 10 * h->ref.L;
   const dim3 g((unsigned)((nt + 255) / 256)), b(256);
+  const size_t L = h->ref.L;
   if (h->prec == DGD_FP64)
-    hipLaunchKernelGGL((k_project<double>), g, b, 0, h->stream, h->ne, h->ref.L, h->ref.Q,
-                       (const double*)h->Pwd.p, (const double*)h->scratch.p,
-                       (double*)h->U9[h->cur].p, (double*)h->Ua[h->cur].p);
+    hipLaunchKernelGGL((k_project<double>), g, b, 0, h->stream, (long long)count, h->ref.L,
+                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       (double*)h->U9[h->cur].p + (size_t)e0 * 9 * L,
+                       (double*)h->Ua[h->cur].p + (size_t)e0 * L);
   else
-    hipLaunchKernelGGL((k_project<float>), g, b, 0, h->stream, h->ne, h->ref.L, h->ref.Q,
-                       (const double*)h->Pwd.p, (const double*)h->scratch.p,
-                       (float*)h->U9[h->cur].p, (double*)h->Ua[h->cur].p);
+    hipLaunchKernelGGL((k_project<float>), g, b, 0, h->stream, (long long)count, h->ref.L,
+                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       (float*)h->U9[h->cur].p + (size_t)e0 * 9 * L,
+                       (double*)h->Ua[h->cur].p + (size_t)e0 * L);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->scratch.release();
@@ -852,6 +901,32 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* out) {
                            h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->scratch.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_set_profiling(dgd_handle* h, int on) {
+  if (!h) return DGD_EINVAL;
+  h->profiling = on != 0;
+  return DGD_OK;
+}
+
+dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms, int64_t* launches) {
+  if (!h || !ms || !launches) return DGD_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& u : h->ev_used) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, u.second.first, u.second.second) == hipSuccess) {
+      ms[u.first] += t;
+      launches[u.first] += 1;
+    }
+    h->ev_pool.push_back(u.second.first);
+    h->ev_pool.push_back(u.second.second);
+  }
+  h->ev_used.clear();
   return DGD_OK;
 }
 

@@ -59,26 +59,23 @@ def cube_mesh(n, length, periodic=False, origin=(0.0, 0.0, 0.0),
         return i + (n + 1) * (j + (n + 1) * k)
 
     perms = list(itertools.permutations(range(3)))
-    tets = []
-    cells = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
-                                 indexing="ij"), axis=-1).reshape(-1, 3)
-    # cube order: i fastest, then j, then k
-    cells = cells[np.lexsort((cells[:, 0], cells[:, 1], cells[:, 2]))]
-    for (ci, cj, ck) in cells:
-        for p in perms:
-            path = [np.array([ci, cj, ck])]
-            cur = path[0].copy()
-            for ax in p:
-                cur = cur.copy()
-                cur[ax] += 1
-                path.append(cur)
-            ids = [vid(*c) for c in path]
-            # parity of the permutation decides the orientation
-            inv = sum(1 for a in range(3) for b in range(a + 1, 3) if p[a] > p[b])
-            if inv % 2 == 1:
-                ids[1], ids[2] = ids[2], ids[1]
-            tets.append(ids)
-    tets = np.asarray(tets, dtype=np.int64)
+    # cube order: i fastest, then j, then k; six tetrahedra per cube in the
+    # order of ``perms`` (path 0 -> e_p0 -> e_p0 + e_p1 -> (1,1,1))
+    ck, cj, ci = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)        # (ncell, 3)
+    tets = np.zeros((base.shape[0], 6, 4), dtype=np.int64)
+    for t, p in enumerate(perms):
+        cur = base.copy()
+        ids = [vid(cur[:, 0], cur[:, 1], cur[:, 2])]
+        for ax in p:
+            cur = cur.copy()
+            cur[:, ax] += 1
+            ids.append(vid(cur[:, 0], cur[:, 1], cur[:, 2]))
+        inv = sum(1 for a in range(3) for b in range(a + 1, 3) if p[a] > p[b])
+        if inv % 2 == 1:
+            ids[1], ids[2] = ids[2], ids[1]
+        tets[:, t, :] = np.stack(ids, axis=1)
+    tets = tets.reshape(-1, 4)
 
     if periodic:
         pm = vid(ijk[:, 0] % n, ijk[:, 1] % n, ijk[:, 2] % n).astype(np.int64)
