@@ -42,7 +42,8 @@ struct dgd_handle {
   RefData ref;
   size_t tsize = 8;  // bytes of the working type
   // reference data on the device
-  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, PwT, wqT, Vd, wqd, Pwd;
+  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Wpk, Vd, wqd, Pwd;
+  int kpl = 0;  // padded mode count of the time-point state layout
   double inv_wsum = 6.0, phi0_mean = 0.0;
   // mesh and material
   long long ne = 0;
@@ -67,7 +68,7 @@ struct dgd_handle {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 
   ~dgd_handle() {
-    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &PwT, &wqT, &Vd, &wqd, &Pwd, &geo, &fgeo,
+    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Wpk, &Vd, &wqd, &Pwd, &geo, &fgeo,
                      &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis};
     for (DevBuf* b : all) b->release();
@@ -189,12 +190,31 @@ dgd_status build_packed(dgd_handle* h) {
                      },
                      DM::MT, KSN));
     }
+  // damage-source projection and cell-average weights in the accurate precision
+  constexpr int PA = Accurate<P>::value;
+  constexpr int KSQA = 64 / Prec<PA>::KS;
+  std::vector<typename HostAF<PA>::type> pp, wp;
+  for (int c = 0; c < DM::NCH; ++c) {
+    append(pp, pack_A<PA>(
+                   [&](int m, int kk) {
+                     int q = 64 * c + kk;
+                     return (m < L && q < Q) ? r.Pw[(size_t)m * Q + q] : 0.0;
+                   },
+                   DM::MT, KSQA));
+    append(wp, pack_A<PA>(
+                   [&](int m, int kk) {
+                     int q = 64 * c + kk;
+                     return q < Q ? r.wq[q] : 0.0;
+                   },
+                   1, KSQA));
+  }
   dgd_status st;
   if ((st = upload(h, h->Vpk, v)) || (st = upload(h, h->Kpk, k)) || (st = upload(h, h->Spk, s)) ||
-      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)))
+      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)) ||
+      (st = upload(h, h->Wpk, wp)))
     return st;
-  std::vector<T> pw(r.Pw.begin(), r.Pw.end()), wq(r.wq.begin(), r.wq.end());
-  if ((st = upload(h, h->PwT, pw)) || (st = upload(h, h->wqT, wq))) return st;
+  h->kpl = KPL;
+  (void)sizeof(T);
   return DGD_OK;
 }
 
@@ -248,8 +268,8 @@ StepArgs<P> make_args(dgd_handle* h) {
   a.Spk = (const AF*)h->Spk.p;
   a.Fpk = (const AF*)h->Fpk.p;
   a.Lpk = (const AF*)h->Lpk.p;
-  a.Pw = (const T*)h->PwT.p;
-  a.wq = (const T*)h->wqT.p;
+  a.Ppk = (const typename Prec<Accurate<P>::value>::AF*)h->Ppk.p;
+  a.Wpk = (const typename Prec<Accurate<P>::value>::AF*)h->Wpk.p;
   a.dt = h->dt;
   a.amax = (T)h->amax;
   a.smin = (T)1e-15;   // guard sqrt(I2) <= 1e-15, i.e. I2 <= 1e-30, in every precision
@@ -409,7 +429,7 @@ dgd_status alloc_state(dgd_handle* h) {
     if ((s = dalloc(h, h->U9[i], E * 9 * L * h->tsize))) return s;
     if ((s = dalloc(h, h->Ua[i], E * L * sizeof(double)))) return s;
   }
-  if ((s = dalloc(h, h->Uz, E * h->ref.Nt * 10 * L * h->tsize))) return s;
+  if ((s = dalloc(h, h->Uz, E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize))) return s;
   if ((s = dalloc(h, h->flag, sizeof(int)))) return s;
   HIPCHK(h, hipMemsetAsync(h->flag.p, 0, sizeof(int), h->stream));
   return DGD_OK;
@@ -933,15 +953,23 @@ dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms, int64_t* launches) {
 dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
   if (!h || !out) return DGD_EINVAL;
   if (!h->have_state) return fail(h, DGD_ESTATE, "no state");
-  const size_t n = (size_t)h->ne * h->ref.Nt * 10 * h->ref.L;
+  // device layout [e][z][l][16] (fragment layout, padded) -> [e][z][p][l]
+  const size_t L = h->ref.L, Nt = h->ref.Nt, K = (size_t)h->kpl;
+  const size_t n = (size_t)h->ne * Nt * K * 16;
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<double> tmp(n);
   if (h->prec == DGD_FP64) {
-    HIPCHK(h, hipMemcpy(out, h->Uz.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(tmp.data(), h->Uz.p, n * sizeof(double), hipMemcpyDeviceToHost));
   } else {
-    std::vector<float> tmp(n);
-    HIPCHK(h, hipMemcpy(tmp.data(), h->Uz.p, n * sizeof(float), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < n; ++i) out[i] = tmp[i];
+    std::vector<float> tf(n);
+    HIPCHK(h, hipMemcpy(tf.data(), h->Uz.p, n * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) tmp[i] = tf[i];
   }
+  for (size_t e = 0; e < (size_t)h->ne; ++e)
+    for (size_t z = 0; z < Nt; ++z)
+      for (size_t p = 0; p < 10; ++p)
+        for (size_t l = 0; l < L; ++l)
+          out[((e * Nt + z) * 10 + p) * L + l] = tmp[((e * Nt + z) * K + l) * 16 + p];
   return DGD_OK;
 }
 

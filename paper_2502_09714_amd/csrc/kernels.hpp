@@ -47,7 +47,7 @@ template <int P> struct StepArgs {
   const double* Ua;     // [E][L] current damage (FP64)
   T* W9;                // [E][9][L] next state
   double* Wa;           // [E][L]
-  T* Uz;                // [E][Nt][10][L] time-point states
+  T* Uz;                // [E][Nt][KPL][16] time-point states, fragment layout
   const double* geo;    // [E][16]: Theta^-1 (row e, column d), |J|
   const double* fgeo;   // [E][4][4]: outward normal, |S_f|/|J|
   const double* mat;    // [E][8]: rho, lambda0, mu0, gamma_r, xi0, C_d
@@ -57,8 +57,8 @@ template <int P> struct StepArgs {
   const AF* Spk;        // Sw^e per chunk
   const AF* Fpk;        // face traces [f][perm]
   const AF* Lpk;        // lift [f][perm]
-  const T* Pw;          // [L][Q]
-  const T* wq;          // [Q]
+  const typename Prec<Accurate<P>::value>::AF* Ppk;   // w_q phi_l(xi_q) per chunk
+  const typename Prec<Accurate<P>::value>::AF* Wpk;   // w_q in every row, per chunk
   double dt;
   T amax, smin, inv_wsum;
   T tau[8], gamma[8];
@@ -98,16 +98,22 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
+  constexpr int PA_ = Accurate<P>::value;
+  using PA = Prec<PA_>;
   using DM = Dims<N>;
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  constexpr int BIG = 64 * 16 > 3 * KPL * 16 ? 64 * 16 : 3 * KPL * 16;
   __shared__ T sD[N + 1][KPL * 16];
-  __shared__ T sY[3 * KPL * 16];
   __shared__ T sW[KPL * 16];
-  __shared__ T sX[64 * 16];
+  // one buffer for: nodal values / tangent blocks / volume integrands of a
+  // 64-point chunk, and the right-hand sides of the CK recursion
+  __shared__ T sB[BIG];
+  T* const sX = sB;
   __shared__ T sA[300];
   __shared__ T sR[NCH * 64];
-  __shared__ T sAcc[42];
+  __shared__ T sAcc[48];
   __shared__ T sJ[9];
 
   const int lane = threadIdx.x;
@@ -116,57 +122,63 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   const Law<T> law{a.amax, a.smin};
 
   for (int i = lane; i < (N + 1) * KPL * 16; i += 64) (&sD[0][0])[i] = T(0);
-  for (int i = lane; i < 3 * KPL * 16; i += 64) sY[i] = T(0);
   for (int i = lane; i < KPL * 16; i += 64) sW[i] = T(0);
-  __syncthreads();
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
-    const int p = i / L, l = i % L;
-    sD[0][l * 16 + p] = p < 9 ? U9[p * L + l] : (T)a.Ua[e * L + l];
+    const int p = i / L, l = i - p * L;
+    sD[0][l * 16 + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
   }
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  T Ji[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Ji[k] = (T)a.geo[e * 16 + k];
+  if (lane < 9) sJ[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
 
-  // 1. cell average of the pointwise tangent and nodal damage rate at t_n
-  T acc[42];
-#pragma unroll
-  for (int k = 0; k < 42; ++k) acc[k] = T(0);
+  // 1. cell average of the pointwise tangent (weighted sum on the matrix cores)
+  //    and nodal damage rate at t_n
+  typename PA::Acc Cav[3];
+  zero_C<PA_, 3>(Cav);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4>(a.Vpk + (size_t)c * 4 * KSL * 64, KSL, sD[0], C, lane);
+    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, sD[0], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     const int q = 64 * c + lane;
+    T ds[6][7];
+    T r = T(0);
     if (q < Q) {
       T u[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
-      T ds[6][7];
       cdm_tangent(u, m, law, ds);
-      const T w = a.wq[q];
+      r = cdm_rate(u, m, law);
+    } else {
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
-        for (int j = 0; j < 7; ++j) acc[k * 7 + j] += w * ds[k][j];
-      sR[q] = cdm_rate(u, m, law);
-    } else {
-      sR[q] = T(0);
+        for (int j = 0; j < 7; ++j) ds[k][j] = T(0);
+    }
+    sR[q] = r;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      __syncthreads();
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * t + jj;
+        sX[lane * 16 + jj] = j < 42 ? ds[j / 7][j % 7] : T(0);
+      }
+      __syncthreads();
+      typename PA::Acc one[1] = {Cav[t]};
+      wave_gemm<PA_, 1, KSQA>(a.Wpk + (size_t)c * KSQA * 64, sX, one, lane);
+      Cav[t] = one[0];
     }
     __syncthreads();
   }
+  // row 0 of every result tile sits in lanes 0..15, register 0
+  if (lane < 16) {
 #pragma unroll
-  for (int k = 0; k < 42; ++k) {
-    const T v = wave_sum(acc[k]) * a.inv_wsum;
-    if (lane == 0) sAcc[k] = v;
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) sJ[k] = Ji[k];
+    for (int t = 0; t < 3; ++t)
+      if (16 * t + lane < 42) sAcc[16 * t + lane] = Cav[t][0] * a.inv_wsum;
   }
   __syncthreads();
 
@@ -186,30 +198,40 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     }
     sA[i] = v;
   }
-  T src = T(0);
-  if (lane < L)
-    for (int q = 0; q < Q; ++q) src += a.Pw[lane * Q + q] * sR[q];
+  // damage source at t_n projected on the modes (lands in column 9 of sW)
+  {
+    typename PA::Acc Cs[MT];
+    zero_C<PA_, MT>(Cs);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Cs, lane);
+    store_C<PA_, MT>(Cs, sW, L, T(1), lane);
+  }
   __syncthreads();
 
-  // 3. Cauchy-Kovalevskaya recursion
+  // 3. Cauchy-Kovalevskaya recursion.  The right-hand-side buffer held nodal
+  // values before: clear it so that its padding rows and columns (read by the
+  // matrix cores against zero A entries) are zero, not stale values.
+  for (int i = lane; i < 3 * KPL * 16; i += 64) sB[i] = T(0);
+  __syncthreads();
 #pragma unroll
   for (int i = 1; i <= N; ++i) {
     for (int idx = lane; idx < 3 * L * 10; idx += 64) {
-      const int ee = idx / (L * 10), l = (idx / 10) % L, p = idx % 10;
+      const int ee = idx / (L * 10), r = idx - ee * L * 10, l = r / 10, p = r - l * 10;
       const T* Ar = sA + ee * 100 + p * 10;
       const T* Dr = &sD[i - 1][l * 16];
       T s = T(0);
 #pragma unroll
       for (int q = 0; q < 10; ++q) s += Dr[q] * Ar[q];
-      sY[(ee * KPL + l) * 16 + p] = s;
+      sB[(ee * KPL + l) * 16 + p] = s;
     }
     __syncthreads();
     Acc C[MT];
     zero_C<P, MT>(C);
-    wave_gemm<P, MT>(a.Kpk, 3 * KSL, sY, C, lane);
+    wave_gemm<P, MT, 3 * KSL>(a.Kpk, sB, C, lane);
     store_C<P, MT>(C, sD[i], L, T(-1), lane);
     __syncthreads();
-    if (i == 1 && lane < L) sD[1][lane * 16 + 9] += src;
+    if (i == 1 && lane < L) sD[1][lane * 16 + 9] += sW[lane * 16 + 9];
     __syncthreads();
   }
 
@@ -222,29 +244,32 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
     for (int k = 0; k < 27; ++k) gacc[c][k] = T(0);
   }
-  T* Uzo = a.Uz + (size_t)e * Nt * 10 * L;
+  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
   const T ir = T(1) / m.rho;
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = sJ[k];
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
     cz[0] = T(1);
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < 10 * L; idx += 64) {
-      const int p = idx / L, l = idx % L;
+    for (int idx = lane; idx < L * 16; idx += 64) {
       T v = T(0);
 #pragma unroll
-      for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][l * 16 + p];
-      sW[l * 16 + p] = v;
-      Uzo[(z * 10 + p) * L + l] = v;
+      for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][idx];
+      sW[idx] = v;
     }
     __syncthreads();
+    // time-point state in the [l][16] fragment layout (padding rows are zero)
+    for (int idx = lane; idx < KPL * 16; idx += 64) Uzo[z * KPL * 16 + idx] = sW[idx];
     const T g = a.gamma[z];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4>(a.Vpk + (size_t)c * 4 * KSL * 64, KSL, sW, C, lane);
+      wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, sW, C, lane);
       store_C<P, 4>(C, sX, 64, T(1), lane);
       __syncthreads();
       const int q = 64 * c + lane;
@@ -277,7 +302,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     }
   }
 
-  // 5. volume contraction  Vol = sum_e Sw^e G^e
+  // 5. volume contraction Vol = sum_e Sw^e G^e and damage source integral
   Acc Vc[MT];
   zero_C<P, MT>(Vc);
 #pragma unroll
@@ -287,24 +312,30 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
       for (int p = 0; p < 16; ++p) sX[lane * 16 + p] = p < 9 ? gacc[c][ee * 9 + p] : T(0);
       __syncthreads();
-      wave_gemm<P, MT>(a.Spk + (size_t)(ee * NCH + c) * MT * (64 / KS) * 64, 64 / KS, sX, Vc, lane);
+      wave_gemm<P, MT, KSQ>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
       __syncthreads();
     }
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) sR[64 * c + lane] = sacc[c];
-  __syncthreads();
-  T srcv = T(0);
-  if (lane < L)
-    for (int q = 0; q < Q; ++q) srcv += a.Pw[lane * Q + q] * sR[q];
   store_C<P, MT>(Vc, sW, L, (T)a.dt, lane);
+  __syncthreads();
+  {
+    typename PA::Acc Cs[MT];
+    zero_C<PA_, MT>(Cs);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Cs, lane);
+    // column 9 of sW is zero (no damage flux): the source takes its place
+    store_C<PA_, MT>(Cs, sX, L, T(1), lane);
+  }
   __syncthreads();
   T* W9 = a.W9 + e * 9 * L;
   for (int idx = lane; idx < 9 * L; idx += 64) {
-    const int p = idx / L, l = idx % L;
+    const int p = idx / L, l = idx - p * L;
     W9[idx] = sD[0][l * 16 + p] + sW[l * 16 + p];
   }
-  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * srcv);
+  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * 16 + 9]);
 }
 
 template <int N, int P>
@@ -328,7 +359,7 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
   const Law<T> law{a.amax, a.smin};
   for (int i = lane; i < KPN * 16; i += 64) sF[i] = T(0);
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  const T* Uze = a.Uz + (size_t)e * Nt * 10 * L;
+  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
   Acc Fc[MT];
   zero_C<P, MT>(Fc);
   __syncthreads();
@@ -340,18 +371,18 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
     for (int z = 0; z < Nt; ++z) {
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm_g<P, NST>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, KSL, Uze + z * 10 * L, L,
-                          L, C, lane);
+      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16, C,
+                             lane);
       store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
     }
     if (kind == 0) {
       const int nf = conn_nface(w), sq = conn_nperm(w);
-      const T* Uzn = a.Uz + (size_t)nb * Nt * 10 * L;
+      const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
       for (int z = 0; z < Nt; ++z) {
         Acc C[NST];
         zero_C<P, NST>(C);
-        wave_gemm_g<P, NST>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64, KSL,
-                            Uzn + z * 10 * L, L, L, C, lane);
+        wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                               Uzn + z * KPL * 16, C, lane);
         store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
       }
     }
@@ -363,7 +394,7 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
     const T fsc = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
     const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
     for (int idx = lane; idx < Ns * Nt; idx += 64) {
-      const int i = idx % Ns, z = idx / Ns;
+      const int z = idx / Ns, i = idx - z * Ns;
       T* um = sTm + z * TS + i * 16;
       T uM[10], F[10];
 #pragma unroll
@@ -382,15 +413,14 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
       for (int k = 0; k < 10; ++k) um[k] = g * F[k];
     }
     __syncthreads();
-    for (int idx = lane; idx < Ns * 10; idx += 64) {
-      const int i = idx / 10, p = idx % 10;
+    for (int idx = lane; idx < Ns * 16; idx += 64) {
       T s = T(0);
 #pragma unroll
-      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + i * 16 + p];
-      sF[i * 16 + p] = s;
+      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + idx];
+      sF[idx] = (idx & 15) < 10 ? s : T(0);
     }
     __syncthreads();
-    wave_gemm<P, MT>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, KSN, sF, Fc, lane);
+    wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sF, Fc, lane);
     __syncthreads();
   }
   store_C<P, MT>(Fc, sTm, L, T(1), lane);
@@ -398,7 +428,7 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
   T* W9 = a.W9 + e * 9 * L;
   bool bad = false;
   for (int idx = lane; idx < 9 * L; idx += 64) {
-    const int p = idx / L, l = idx % L;
+    const int p = idx / L, l = idx - p * L;
     const T v = W9[idx] - sTm[l * 16 + p];
     bad |= !isfinite(v);
     W9[idx] = v;

@@ -47,10 +47,8 @@ template <> struct Prec<PREC_F64> {
   __device__ static inline AF loadB(const T* B, int s, int lane) {
     return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
   }
-  // B fragment straight from global memory: B[k][n] = g[n * ld + k] for n < 10, k < kmax
-  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
-    int n = lane & 15, k = KS * s + (lane >> 4);
-    return (n < 10 && k < kmax) ? g[n * ld + k] : 0.0;
+  __device__ static inline AF loadB9(const T* v, int s, int lane) {
+    return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0;
   }
 };
 
@@ -66,9 +64,8 @@ template <> struct Prec<PREC_F32> {
   __device__ static inline AF loadB(const T* B, int s, int lane) {
     return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
   }
-  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
-    int n = lane & 15, k = KS * s + (lane >> 4);
-    return (n < 10 && k < kmax) ? g[n * ld + k] : 0.0f;
+  __device__ static inline AF loadB9(const T* v, int s, int lane) {
+    return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0f;
   }
 };
 
@@ -90,43 +87,49 @@ template <> struct Prec<PREC_BF16> {
     r[3] = (short)f32_to_bf16(B[(k0 + 3) * 16 + n]);
     return r;
   }
-  __device__ static inline AF loadBg(const T* g, int ld, int kmax, int s, int lane) {
-    int n = lane & 15, k0 = KS * s + 4 * (lane >> 4);
+  __device__ static inline AF loadB9(const T* v, int s, int lane) {
+    int k0 = KS * s + 4 * (lane >> 4);
+    const bool on = (lane & 15) == 9;
     AF r;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float v = (n < 10 && k0 + j < kmax) ? g[n * ld + k0 + j] : 0.0f;
-      r[j] = (short)f32_to_bf16(v);
-    }
+    for (int j = 0; j < 4; ++j) r[j] = (short)f32_to_bf16(on ? v[k0 + j] : 0.0f);
     return r;
   }
 };
 
 __host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane]
-template <int P, int MT>
-__device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk, int ksteps,
+// The cell average of the tangent and the damage-source projections keep FP32
+// matrix-core inputs in the BF16 form (they feed the FP64 damage update).
+template <int P> struct Accurate { static constexpr int value = P == PREC_BF16 ? PREC_F32 : P; };
+
+// C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane].
+// KSTEPS is a compile-time constant so that the loop unrolls and the A-fragment
+// loads are issued ahead of the matrix-core instructions that consume them.
+template <int P, int MT, int KSTEPS, int KSTRIDE = KSTEPS>
+__device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
                                  const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT],
                                  int lane) {
   using PR = Prec<P>;
-  for (int s = 0; s < ksteps; ++s) {
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
     typename PR::AF b = PR::loadB(B, s, lane);
 #pragma unroll
-    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * ksteps + s) * 64 + lane], b, C[t]);
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
   }
 }
 
-// Same with B read from global memory (per-element state [10][ld])
-template <int P, int MT>
-__device__ inline void wave_gemm_g(const typename Prec<P>::AF* __restrict__ Apk, int ksteps,
-                                   const typename Prec<P>::T* __restrict__ g, int ld, int kmax,
-                                   typename Prec<P>::Acc (&C)[MT], int lane) {
+// C += A x B with B[k][n] = (n == 9) ? v[k] : 0 (a vector placed in the damage column)
+template <int P, int MT, int KSTEPS>
+__device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ Apk,
+                                      const typename Prec<P>::T* v, typename Prec<P>::Acc (&C)[MT],
+                                      int lane) {
   using PR = Prec<P>;
-  for (int s = 0; s < ksteps; ++s) {
-    typename PR::AF b = PR::loadBg(g, ld, kmax, s, lane);
 #pragma unroll
-    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * ksteps + s) * 64 + lane], b, C[t]);
+  for (int s = 0; s < KSTEPS; ++s) {
+    typename PR::AF b = PR::loadB9(v, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTEPS + s) * 64 + lane], b, C[t]);
   }
 }
 
