@@ -46,8 +46,11 @@ class OracleSolver:
     """Plain FP64 CPU reference solver for one workload."""
 
     def __init__(self, xyz, tets, face_tag, periodic_map, material, N, dt,
-                 alpha_max=0.5, i2_min=cdm.I2_MIN_F64):
+                 alpha_max=0.5, i2_min=cdm.I2_MIN_F64, llf_speed=None):
         self.N = N
+        # largest eigenvalue of B_n (Eq. rusanov-flux); replaceable by an
+        # equal, differentiable form (oracle.adjoint)
+        self.llf_speed = cdm.llf_speed if llf_speed is None else llf_speed
         self.ref = RefElement(N)
         self.mesh = OracleMesh(xyz, tets, face_tag, periodic_map, self.ref)
         self.E = self.mesh.E
@@ -156,8 +159,8 @@ class OracleSolver:
                     FM = torch.einsum("mid,midp->mip", n, cdm.flux(uM, mat_m, am, i2))
                     FP = torch.einsum("mid,midp->mip", n, cdm.flux(uP, mat_p, am, i2))
                     ubar = 0.5 * (uM + uP)
-                    C = torch.maximum(cdm.llf_speed(ubar, n, mat_m, am, i2),
-                                      cdm.llf_speed(ubar, n, mat_p, am, i2))
+                    C = torch.maximum(self.llf_speed(ubar, n, mat_m, am, i2),
+                                      self.llf_speed(ubar, n, mat_p, am, i2))
                     Fs = 0.5 * (FM + FP) + 0.5 * C[..., None] * (uM - uP)
                     acc = acc + ref.gamma[z] * Fs
                 out[me, f] = acc
