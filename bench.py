@@ -27,7 +27,8 @@ if ROOT not in sys.path:
 METRIC = "DG DOF-updates/s on 1 GPU, FP32/BF16 vs FP64 at stated L2 error; adjoint/forward cost"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 HBM_TBS = 8.0
-KERNELS = ("predict_volume", "face_update", "sources", "receivers")
+KERNELS = ("predict_volume", "face_update", "sources", "receivers",
+           "adj_predict_recompute", "adj_face", "adj_volume", "adj_receivers")
 
 
 def dims(N):
@@ -113,6 +114,46 @@ def run_precision(w, prec, steps, warmup, want_state=True):
     return out
 
 
+def run_adjoint(w, prec, steps, every):
+    """Checkpointed forward run (seismograms recorded) and the backward sweep
+    for the misfit J = |seismograms|^2 / 2: wall time of each and the
+    per-kernel times of the backward sweep."""
+    import torch
+    from paper_2502_09714_amd.api import from_workload
+    sim = from_workload(w, prec)
+    if sim.nrec == 0:
+        m = w.mesh
+        cent = m["xyz"][m["tets"][[0, w.ne // 3, w.ne // 2, (2 * w.ne) // 3]]].mean(axis=1)
+        sim.set_receivers(cent)
+    sim.set_check_interval(1 << 40)
+    sim.forward_checkpointed(2, 1)          # warm-up of both sweeps
+    sim.backward(sim.get_seismograms())
+    sim.clear_seismograms()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_checkpointed(steps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seis = sim.get_seismograms()
+    sim.get_kernel_times()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gmu, gcd = sim.backward(seis)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ms, launches = sim.get_kernel_times()
+    sim.set_profiling(False)
+    sim.close()
+    import numpy as np
+    return {"forward_s": t1 - t0, "backward_s": t3 - t2,
+            "backward_over_forward": (t3 - t2) / (t1 - t0),
+            "backward_kernel_ms_per_step": {k: float(ms[i]) / steps for i, k in enumerate(KERNELS)
+                                            if launches[i] > 0},
+            "steps": steps, "checkpoint_every": every,
+            "finite": bool(np.isfinite(gmu).all() and np.isfinite(gcd).all())}
+
+
 def rel_l2(a, b):
     import numpy as np
     out = {}
@@ -153,6 +194,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=6)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--adjoint-precisions", default="fp32,fp64",
+                    help="precisions whose checkpointed adjoint is timed ('' for none)")
+    ap.add_argument("--checkpoint-every", type=int, default=5)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -228,6 +272,10 @@ def main():
             if p != "fp64":
                 line[f"speedup_{p}_vs_fp64"] = rate(p) / rate("fp64")
                 line[f"l2_{p}_vs_fp64_gpu"] = rel_l2(res[p]["state"], res["fp64"]["state"])
+    for p in [q.strip() for q in args.adjoint_precisions.split(",") if q.strip()]:
+        a = run_adjoint(w, p, args.steps, args.checkpoint_every)
+        print(f"adjoint {p}: {a}", file=sys.stderr, flush=True)
+        line[f"adjoint_{p}"] = a
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n, args.cpu_steps)
     print(json.dumps(line), flush=True)

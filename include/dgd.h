@@ -158,16 +158,62 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
 
 /* Per-kernel timing with HIP events recorded on the solver's stream around
  * every launch while profiling is on.  dgd_get_kernel_times synchronises,
- * returns the summed milliseconds and launch counts of the kernels
- * {0: predictor + volume, 1: faces + update, 2: sources, 3: receivers}
+ * returns the summed milliseconds and launch counts of the kernel classes
+ * {0: predictor + volume, 1: faces + update, 2: sources, 3: receivers,
+ *  4: adjoint's predictor recomputation, 5: adjoint faces, 6: adjoint
+ *  volume + predictor, 7: adjoint receivers}
  * since the last call, and resets them. */
+#define DGD_NUM_KERNEL_CLASSES 8
 dgd_status dgd_set_profiling(dgd_handle* h, int on);
-dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms /* 4 */, int64_t* launches /* 4 */);
+dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms /* 8 */, int64_t* launches /* 8 */);
 
 /* Intermediate results of the last dgd_step call for testing: the time-point
  * states U(t_n + tau_z dt) of its last step, [ne][Nt][10][L] FP64 host.
  * Synchronises. */
 dgd_status dgd_get_time_point_states(dgd_handle* h, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint (gradients of a seismogram misfit).
+ *
+ * The paper computes forward seismograms only; these calls differentiate the
+ * discrete step defined by the calls above (Appendix A.1-A.3 with the CDM law
+ * of Eq. cdb-model) exactly, with respect to the state and to the per-element
+ * shear modulus mu0 and damage coefficient C_d of Eq. cdb-model.  Conventions
+ * at the non-smooth points of the step: d clamp(alpha)/d alpha = 1 on the
+ * closed interval [0, alpha_max]; the damage rate and the sqrt(I2) terms have
+ * zero derivative where they are switched off (xi <= xi0, sqrt(I2) <= 1e-15);
+ * at a tie of the two sides' Lax-Friedrichs speeds (Eq. rusanov-flux) each
+ * side takes half of the derivative.  Point sources do not depend on the
+ * state or on mu0, C_d.  Runs in FP64 or FP32 (DGD_BF16 handles return
+ * DGD_EINVAL); the adjoint arithmetic has the handle's precision.
+ *
+ * dgd_adjoint_step: one step's vector-Jacobian product at the current state
+ * U^n (left unchanged):  lam_out = (dU^{n+1}/dU^n)^T lam_next,
+ * grad_mu0[e] = lam_next . dU^{n+1}/dmu0_e, grad_cd[e] likewise (both may be
+ * NULL).  lam_next, lam_out: [ne][10][L] FP64 host; gradients: [ne] FP64
+ * host.  Synchronises.
+ *
+ * dgd_forward_checkpointed: runs nsteps steps from the current state like
+ * dgd_step (seismograms recorded as usual), keeping a device copy of the
+ * state every `every` steps (ceil(nsteps/every) copies) for dgd_backward.
+ * Synchronises (and reports DGD_ENUMERIC like dgd_synchronize).
+ *
+ * dgd_backward: gradients of a scalar misfit J(seismograms) of the last
+ * checkpointed run, given dl_dseis = dJ/dseismograms [nsteps][nrec][3] FP64
+ * host (the seismograms that run recorded, in recording order; may be NULL
+ * without receivers).  Each segment of `every` steps is recomputed from its
+ * checkpoint and then reversed.  Outputs (host, overwritten):
+ * grad_mu0[ne], grad_cd[ne], and if grad_u0 is not NULL dJ/dU^0 as
+ * [ne][10][L].  The current state, time and seismograms are left as the
+ * forward run left them; the checkpoints are kept until the next
+ * dgd_forward_checkpointed or dgd_release_tape.  Synchronises.
+ */
+dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_out,
+                            double* grad_mu0, double* grad_cd);
+dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every);
+dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0, double* grad_cd,
+                        double* grad_u0);
+dgd_status dgd_release_tape(dgd_handle* h);
 
 #ifdef __cplusplus
 }

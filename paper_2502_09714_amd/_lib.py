@@ -50,7 +50,12 @@ _SIGS = {
     "dgd_get_time_point_states": (ctypes.c_int, [H, c_dp]),
     "dgd_set_profiling": (ctypes.c_int, [H, ctypes.c_int]),
     "dgd_get_kernel_times": (ctypes.c_int, [H, c_dp, c_i64p]),
+    "dgd_adjoint_step": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
+    "dgd_forward_checkpointed": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64]),
+    "dgd_backward": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
+    "dgd_release_tape": (ctypes.c_int, [H]),
 }
+NUM_KERNEL_CLASSES = 8
 
 
 def lib():

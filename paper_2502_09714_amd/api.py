@@ -7,7 +7,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import DGDError, FP32, FP64, BF16, c_dp, c_i8p, c_i64p, lib
+from ._lib import DGDError, FP32, FP64, BF16, NUM_KERNEL_CLASSES, c_dp, c_i8p, c_i64p, lib
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -76,6 +76,7 @@ class Simulation:
     def set_material(self, rho, lambda0, mu0, gamma_r, xi0, Cd):
         arrs = [_f64(a) for a in (rho, lambda0, mu0, gamma_r, xi0, Cd)]
         self._chk(self._L.dgd_set_material(self.h, *[_dp(a) for a in arrs]))
+        self.material = dict(zip(("rho", "lambda0", "mu0", "gamma_r", "xi0", "Cd"), arrs))
 
     def set_params(self, dt, alpha_max):
         self._chk(self._L.dgd_set_params(self.h, float(dt), float(alpha_max)))
@@ -167,11 +168,39 @@ class Simulation:
         self._chk(self._L.dgd_set_profiling(self.h, int(bool(on))))
 
     def get_kernel_times(self):
-        """(ms[4], launches[4]) for predictor+volume, faces+update, sources, receivers."""
-        ms = np.zeros(4)
-        n = np.zeros(4, dtype=np.int64)
+        """(ms[8], launches[8]) for predictor+volume, faces+update, sources,
+        receivers, and the adjoint's predictor recomputation, faces, volume,
+        receivers."""
+        ms = np.zeros(NUM_KERNEL_CLASSES)
+        n = np.zeros(NUM_KERNEL_CLASSES, dtype=np.int64)
         self._chk(self._L.dgd_get_kernel_times(self.h, _dp(ms), n.ctypes.data_as(c_i64p)))
         return ms, n
+
+    # ---- discrete adjoint ----------------------------------------------------------
+    def adjoint_step(self, lam_next):
+        """(lam_n, grad_mu0, grad_cd) of one step at the current state."""
+        lam = _f64(lam_next, (self.ne, 10, self.L))
+        out = np.zeros((self.ne, 10, self.L))
+        gmu = np.zeros(self.ne)
+        gcd = np.zeros(self.ne)
+        self._chk(self._L.dgd_adjoint_step(self.h, _dp(lam), _dp(out), _dp(gmu), _dp(gcd)))
+        return out, gmu, gcd
+
+    def forward_checkpointed(self, nsteps, every):
+        self._chk(self._L.dgd_forward_checkpointed(self.h, int(nsteps), int(every)))
+
+    def backward(self, dl_dseis, want_u0=False):
+        """(grad_mu0, grad_cd[, grad_u0]) of the last checkpointed run."""
+        g = None if (self.nrec == 0 or dl_dseis is None) else _f64(dl_dseis)
+        gmu = np.zeros(self.ne)
+        gcd = np.zeros(self.ne)
+        gu = np.zeros((self.ne, 10, self.L)) if want_u0 else None
+        self._chk(self._L.dgd_backward(self.h, None if g is None else _dp(g), _dp(gmu), _dp(gcd),
+                                       None if gu is None else _dp(gu)))
+        return (gmu, gcd, gu) if want_u0 else (gmu, gcd)
+
+    def release_tape(self):
+        self._chk(self._L.dgd_release_tape(self.h))
 
     def get_time_point_states(self):
         out = np.zeros((self.ne, self.Nt, 10, self.L))

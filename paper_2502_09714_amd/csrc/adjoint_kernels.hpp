@@ -1,0 +1,433 @@
+// Discrete adjoint of one ADER-DG step (device), transposing every stage of
+// k_predict_volume / k_face_update:  given U^n and lambda^{n+1} = dJ/dU^{n+1}
+// it returns lambda^n = dJ/dU^n and accumulates dJ/dmu0, dJ/dC_d per element.
+//
+//   k_predict_volume (forward, recomputed)  ->  time-point states U_z of all elements
+//   k_adj_face   face terms: traces of U_z and of lambda at the shared face points,
+//                cotangent of the single-valued flux from both neighbours' updates,
+//                flux VJP, transposed trace (lift) -> dJ/dU_z (face part)
+//   k_adj_volume predictor recomputed; volume / source VJP at every (z, q);
+//                transposed nodal evaluation; Taylor and CK recursion reversed;
+//                cell-averaged-tangent VJP (second derivatives of the stress);
+//                identity path -> lambda^n
+// One wavefront per element; every element writes only its own outputs.
+#pragma once
+#include "adjoint_point.hpp"
+#include "kernels.hpp"
+
+namespace dgd {
+
+template <int P> struct AdjArgs {
+  using T = typename Prec<P>::T;
+  using AF = typename Prec<P>::AF;
+  StepArgs<P> s;          // forward data (U^n in s.U9 / s.Ua, time points in s.Uz)
+  const T* lam;           // [E][KPL][16] lambda^{n+1}
+  T* lamOut;              // [E][KPL][16] lambda^n
+  T* lzf;                 // [E][Nt][KPL][16] face part of dJ/dU_z
+  const AF* VTpk;         // V^T per chunk        (L x 64)
+  const AF* STpk;         // Sw^e^T per e, chunk  (64 x L)
+  const AF* PTpk;         // Pw^T per chunk       (64 x L)
+  const AF* KTpk;         // K^e^T per e          (L x L)
+  const double* wq;       // [Q] volume weights
+  const double* beta;     // [Ns] face weights
+  double* gmu;            // [E] dJ/dmu0 (accumulated)
+  double* gcd;            // [E] dJ/dC_d (accumulated)
+};
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  const StepArgs<P>& a = A.s;
+  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
+  constexpr int TS = NST * 16 * 16;
+  static_assert(TS >= KPN * 16, "face buffer too small");
+  __shared__ T sTm[Nt * TS];
+  __shared__ T sTp[Nt * TS];
+  __shared__ T sLm[TS];
+  __shared__ T sLp[TS];
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  for (int i = lane; i < Nt * TS; i += 64) sTm[i] = T(0);
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  const T* Le = A.lam + (size_t)e * KPL * 16;
+  Acc Cz[Nt][MT];
+#pragma unroll
+  for (int z = 0; z < Nt; ++z) zero_C<P, MT>(Cz[z]);
+  T gmu = T(0);
+
+  for (int f = 0; f < 4; ++f) {
+    const int nb = a.conn[(e * 4 + f) * 2];
+    const int w = a.conn[(e * 4 + f) * 2 + 1];
+    const int kind = conn_kind(w), sp = conn_perm(w);
+    const int nf = conn_nface(w), sq = conn_nperm(w);
+    __syncthreads();
+    for (int z = 0; z < Nt; ++z) {
+      Acc C[NST];
+      zero_C<P, NST>(C);
+      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16, C,
+                             lane);
+      store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+    }
+    {
+      Acc C[NST];
+      zero_C<P, NST>(C);
+      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Le, C, lane);
+      store_C<P, NST>(C, sLm, Ns, T(1), lane);
+    }
+    if (kind == 0) {
+      const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+      for (int z = 0; z < Nt; ++z) {
+        Acc C[NST];
+        zero_C<P, NST>(C);
+        wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                               Uzn + z * KPL * 16, C, lane);
+        store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
+      }
+      Acc C[NST];
+      zero_C<P, NST>(C);
+      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                             A.lam + (size_t)nb * KPL * 16, C, lane);
+      store_C<P, NST>(C, sLp, Ns, T(1), lane);
+    }
+    __syncthreads();
+    T n[3];
+    n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
+    n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
+    n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
+    // update of e: -dt |S|/|J_e| Lift F*;  update of the neighbour: +dt |S|/|J_nb| Lift' F*
+    const T se = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
+    const T sn = kind == 0 ? (T)(a.fgeo[((size_t)nb * 4 + nf) * 4 + 3] * a.dt) : T(0);
+    const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
+    for (int idx = lane; idx < Ns * Nt; idx += 64) {
+      const int z = idx / Ns, i = idx - z * Ns;
+      T* um = sTm + z * TS + i * 16;
+      T uM[10], wv[10], gu[10];
+      T gm = T(0);
+      const T g = a.gamma[z];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        uM[k] = um[k];
+        gu[k] = T(0);
+      }
+      if (kind == 0) {
+        T uP[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+          uP[k] = sTp[z * TS + i * 16 + k];
+          wv[k] = g * (-se * sLm[i * 16 + k] + sn * sLp[i * 16 + k]);
+        }
+        llf_vjp_minus(uM, uP, n, m, mp, law, wv, gu, gm);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) wv[k] = g * (-se * sLm[i * 16 + k]);
+        boundary_vjp(kind, uM, n, m, law, wv, gu, gm);
+      }
+      // the state cotangent takes the face weight through the lift below;
+      // the material cotangent takes it here
+      gmu += (T)A.beta[i] * gm;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) um[k] = k < 10 ? gu[k] : T(0);
+    }
+    __syncthreads();
+    // transposed trace: the lift matrix carries the face weights beta_i
+#pragma unroll
+    for (int z = 0; z < Nt; ++z)
+      wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sTm + z * TS, Cz[z],
+                            lane);
+  }
+#pragma unroll
+  for (int z = 0; z < Nt; ++z)
+    store_C<P, MT>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
+  const T gs = wave_sum(gmu);
+  if (lane == 0) A.gmu[e] += (double)gs;
+}
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  const StepArgs<P>& a = A.s;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
+  __shared__ PredLDS<N, P> S;
+  __shared__ T sLam[KPL * 16];
+  __shared__ T sLU[Nt][KPL * 16];
+  __shared__ T sLD[N + 1][KPL * 16];
+  __shared__ T sLA[300];
+  __shared__ T sLds[48];
+  T* const sX = S.B;
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  predictor_stage<N, P>(a, e, S, m, lane);
+  for (int i = lane; i < KPL * 16; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
+  for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
+  const T ir = T(1) / m.rho;
+  T gmu = T(0), gcd = T(0);
+  __syncthreads();
+
+  // dJ/dG^e at the volume points: dt Sw^e^T lambda;  dJ/dr: dt Pw^T lambda_alpha
+  T LG[NCH][27];
+  T Ls[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+    for (int ee = 0; ee < 3; ++ee) {
+      Acc C[4];
+      zero_C<P, 4>(C);
+      wave_gemm<P, 4, KSL>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C, lane);
+      store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 9; ++p) LG[c][ee * 9 + p] = sX[lane * 16 + p];
+      __syncthreads();
+    }
+    Acc C[4];
+    zero_C<P, 4>(C);
+    wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
+    store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
+    __syncthreads();
+    Ls[c] = sX[lane * 16 + 9];
+    __syncthreads();
+  }
+
+  // volume and source cotangents at every time point -> dJ/dU_z
+  for (int z = 0; z < Nt; ++z) {
+    T cz[N + 1];
+    cz[0] = T(1);
+    const T h = a.tau[z] * (T)a.dt;
+#pragma unroll
+    for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+    for (int idx = lane; idx < L * 16; idx += 64) {
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i <= N; ++i) v += cz[i] * S.D[i][idx];
+      S.W[idx] = v;
+    }
+    __syncthreads();
+    const T g = a.gamma[z];
+    Acc Cl[MT];
+    zero_C<P, MT>(Cl);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      Acc C[4];
+      zero_C<P, 4>(C);
+      wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.W, C, lane);
+      store_C<P, 4>(C, sX, 64, T(1), lane);
+      __syncthreads();
+      const int q = 64 * c + lane;
+      T gu[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) gu[k] = T(0);
+      if (q < Q) {
+        T u[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+        // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
+        T ls[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ee = 0; ee < 3; ++ee) {
+          const T* Jr = Ji + ee * 3;
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+            const int ii = kVI[p], jj = kVJ[p];
+            const T lg = g * LG[c][ee * 9 + p];
+            gu[6 + ii] += T(-0.5) * Jr[jj] * lg;
+            gu[6 + jj] += T(-0.5) * Jr[ii] * lg;
+          }
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) {
+            const T lg = g * LG[c][ee * 9 + 6 + ii] * (-ir);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ls[sym_idx(ii, d)] += lg * Jr[d];
+          }
+        }
+        stress_vjp(u, m, law, ls, gu, gmu);
+        rate_vjp(u, m, law, g * Ls[c], gu, gcd);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sX[lane * 16 + k] = k < 10 ? gu[k] : T(0);
+      __syncthreads();
+      wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cl, lane);
+      __syncthreads();
+    }
+    store_C<P, MT>(Cl, sLU[z], KPL, T(1), lane);
+    __syncthreads();
+    const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
+    for (int idx = lane; idx < KPL * 16; idx += 64) sLU[z][idx] += lz[idx];
+    __syncthreads();
+  }
+
+  // Taylor series reversed: dJ/dD^i = sum_z (tau_z dt)^i / i! dJ/dU_z
+  for (int idx = lane; idx < KPL * 16; idx += 64) {
+#pragma unroll
+    for (int i = 0; i <= N; ++i) sLD[i][idx] = T(0);
+  }
+  for (int z = 0; z < Nt; ++z) {
+    T cz = T(1);
+    const T h = a.tau[z] * (T)a.dt;
+    for (int i = 0; i <= N; ++i) {
+      if (i > 0) cz = cz * h / T(i);
+      for (int idx = lane; idx < KPL * 16; idx += 64) sLD[i][idx] += cz * sLU[z][idx];
+    }
+  }
+  __syncthreads();
+
+  // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source)
+  for (int i = N; i >= 1; --i) {
+#pragma unroll
+    for (int ee = 0; ee < 3; ++ee) {
+      Acc C[MT];
+      zero_C<P, MT>(C);
+      wave_gemm<P, MT, KSL>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
+      store_C<P, MT>(C, S.B + ee * KPL * 16, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
+    }
+    __syncthreads();
+    // dJ/dD^{i-1} += sum_e dJ/dY_e A*_e
+    for (int idx = lane; idx < L * 10; idx += 64) {
+      const int l = idx / 10, q = idx - l * 10;
+      T s = T(0);
+#pragma unroll
+      for (int ee = 0; ee < 3; ++ee)
+#pragma unroll
+        for (int p = 0; p < 10; ++p) s += S.B[(ee * KPL + l) * 16 + p] * S.A[ee * 100 + p * 10 + q];
+      sLD[i - 1][l * 16 + q] += s;
+    }
+    // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]
+    for (int idx = lane; idx < 300; idx += 64) {
+      const int ee = idx / 100, p = (idx / 10) % 10, q = idx % 10;
+      T s = T(0);
+      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * 16 + p] * S.D[i - 1][l * 16 + q];
+      sLA[idx] += s;
+    }
+    __syncthreads();
+  }
+  // damage source at t_n: dJ/dr_q = (Pw^T dJ/dD^1)_q in column 9
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    Acc C[4];
+    zero_C<P, 4>(C);
+    wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
+    store_C<P, 4>(C, sX, 64, T(1), lane);
+    __syncthreads();
+    S.R[64 * c + lane] = sX[lane * 16 + 9];
+    __syncthreads();
+  }
+  // dJ/dBbar through A*_e[6+i][q] = -(1/rho) sum_d Theta^-1_ed dsbar[sym(i,d)][col(q)]
+  if (lane < 42) {
+    const int k = lane / 7, c = lane % 7, q = c < 6 ? c : 9;
+    T s = T(0);
+#pragma unroll
+    for (int ee = 0; ee < 3; ++ee)
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (sym_idx(ii, d) == k) s += -ir * Ji[ee * 3 + d] * sLA[ee * 100 + (6 + ii) * 10 + q];
+    sLds[lane] = s;
+  }
+  __syncthreads();
+  // mu0 enters the tangent as 2 mu0 on the strain diagonal (the average keeps it)
+  if (lane == 0) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s += T(2) * sLds[k * 7 + k];
+    gmu += s;
+  }
+  // pointwise tangent and source cotangents at t_n -> dJ/dU^n (nodal path)
+  T lt[6][7];
+  Acc Cu[MT];
+  zero_C<P, MT>(Cu);
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    Acc C[4];
+    zero_C<P, 4>(C);
+    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
+    store_C<P, 4>(C, sX, 64, T(1), lane);
+    __syncthreads();
+    const int q = 64 * c + lane;
+    T gu[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gu[k] = T(0);
+    if (q < Q) {
+      T u[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+      const T wgt = (T)A.wq[q] * a.inv_wsum;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) lt[k][j] = wgt * sLds[k * 7 + j];
+      tangent_vjp(u, m, law, lt, gu);
+      rate_vjp(u, m, law, S.R[q], gu, gcd);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sX[lane * 16 + k] = k < 10 ? gu[k] : T(0);
+    __syncthreads();
+    wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cu, lane);
+    __syncthreads();
+  }
+  store_C<P, MT>(Cu, S.W, KPL, T(1), lane);
+  __syncthreads();
+  // lambda^n = lambda^{n+1} (identity) + dJ/dD^0 + nodal path
+  T* out = A.lamOut + (size_t)e * KPL * 16;
+  for (int idx = lane; idx < KPL * 16; idx += 64) out[idx] = sLam[idx] + sLD[0][idx] + S.W[idx];
+  const T gm = wave_sum(gmu), gc = wave_sum(gcd);
+  if (lane == 0) {
+    A.gmu[e] += (double)gm;
+    A.gcd[e] += (double)gc;
+  }
+}
+
+// receiver misfit: lambda[e_r][l][6+c] += dL/dv_rc phi_l(xi_r)
+template <class T>
+__global__ void k_adj_receivers(int nrec, int L, int kpl, const long long* elem, const double* phi,
+                                const double* dldv, T* lam) {
+  const int idx = threadIdx.x;   // (c, l)
+  if (idx >= 3 * L) return;
+  const int c = idx / L, l = idx % L;
+  for (int r = 0; r < nrec; ++r) {
+    T* dst = lam + ((size_t)elem[r] * kpl + l) * 16 + 6 + c;
+    *dst = (T)((double)*dst + dldv[r * 3 + c] * phi[r * L + l]);
+  }
+}
+
+// layout conversions of the adjoint state: [E][10][L] FP64 <-> [E][KPL][16]
+template <class T>
+__global__ void k_lam_from_f64(long long E, int L, int kpl, const double* in, T* lam) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * kpl * 16) return;
+  const long long e = idx / (kpl * 16);
+  const int r = (int)(idx % (kpl * 16)), l = r / 16, p = r % 16;
+  lam[idx] = (l < L && p < 10) ? (T)in[(e * 10 + p) * L + l] : T(0);
+}
+
+template <class T>
+__global__ void k_lam_to_f64(long long E, int L, int kpl, const T* lam, double* out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * 10 * L) return;
+  const long long e = idx / (10 * L);
+  const int p = (int)((idx / L) % 10), l = (int)(idx % L);
+  out[idx] = (double)lam[(e * kpl + l) * 16 + p];
+}
+
+}  // namespace dgd

@@ -1,0 +1,284 @@
+// Pointwise derivatives for the discrete adjoint of the CDM step (device).
+//
+// Vector-Jacobian products of every pointwise map of the forward step, with
+// respect to the state u (10 quantities) and the shear modulus mu0 (and C_d
+// where it enters).  Conventions shared with the forward kernels:
+//   * alpha clamp: derivative 1 on the closed interval [0, alpha_max], else 0;
+//   * damage-rate threshold xi > xi0 and the sqrt(I2) guard: derivative 0 on
+//     the inactive side;
+//   * LLF constant C = max(c-, c+): at an exact tie each side takes one half.
+// Flux and stress products are exact through the hand-written tangent; the
+// derivatives of the tangent itself (predictor) and of the boundary fluxes use
+// forward-mode dual numbers; the derivative of the largest acoustic-tensor
+// eigenvalue uses its eigenvector (v^T dQ v), which stays well defined when
+// the two smaller eigenvalues coincide.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace dgd {
+
+// the overloads for Dual below must not hide the scalar ones
+using ::fabs;
+using ::fmax;
+using ::sqrt;
+
+template <class T> struct Dual {
+  T v, d;
+  __device__ Dual() : v(0), d(0) {}
+  __device__ Dual(T a, T b) : v(a), d(b) {}
+  __device__ Dual(double a) : v(T(a)), d(T(0)) {}
+  __device__ Dual(float a) : v(T(a)), d(T(0)) {}
+  __device__ Dual(int a) : v(T(a)), d(T(0)) {}
+};
+
+template <class T> __device__ inline Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <class T> __device__ inline Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <class T> __device__ inline Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
+template <class T> __device__ inline Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class T> __device__ inline Dual<T> operator/(Dual<T> a, Dual<T> b) {
+  const T iv = T(1) / b.v;
+  return {a.v * iv, (a.d - a.v * iv * b.d) * iv};
+}
+template <class T> __device__ inline Dual<T>& operator+=(Dual<T>& a, Dual<T> b) { a = a + b; return a; }
+template <class T> __device__ inline Dual<T>& operator-=(Dual<T>& a, Dual<T> b) { a = a - b; return a; }
+template <class T> __device__ inline Dual<T>& operator*=(Dual<T>& a, Dual<T> b) { a = a * b; return a; }
+template <class T> __device__ inline bool operator<(Dual<T> a, Dual<T> b) { return a.v < b.v; }
+template <class T> __device__ inline bool operator>(Dual<T> a, Dual<T> b) { return a.v > b.v; }
+template <class T> __device__ inline bool operator<=(Dual<T> a, Dual<T> b) { return a.v <= b.v; }
+template <class T> __device__ inline bool operator>=(Dual<T> a, Dual<T> b) { return a.v >= b.v; }
+template <class T> __device__ inline Dual<T> sqrt(Dual<T> a) {
+  const T s = ::sqrt(a.v);
+  return {s, s > T(0) ? a.d / (T(2) * s) : T(0)};
+}
+template <class T> __device__ inline Dual<T> fabs(Dual<T> a) { return a.v < T(0) ? -a : a; }
+template <class T> __device__ inline Dual<T> fmax(Dual<T> a, Dual<T> b) { return a.v >= b.v ? a : b; }
+
+template <class T>
+__device__ inline MatP<Dual<T>> dual_mat(const MatP<T>& m, bool seed_mu) {
+  MatP<Dual<T>> r;
+  r.rho = Dual<T>(m.rho, T(0));
+  r.lam = Dual<T>(m.lam, T(0));
+  r.mu = Dual<T>(m.mu, seed_mu ? T(1) : T(0));
+  r.gr = Dual<T>(m.gr, T(0));
+  r.xi0 = Dual<T>(m.xi0, T(0));
+  r.cd = Dual<T>(m.cd, T(0));
+  return r;
+}
+
+template <class T>
+__device__ inline Law<Dual<T>> dual_law(const Law<T>& l) {
+  return Law<Dual<T>>{Dual<T>(l.amax, T(0)), Dual<T>(l.smin, T(0))};
+}
+
+// seed direction j (0..9) of the state; j = 10 seeds nothing (material pass)
+template <class T>
+__device__ inline void dual_state(const T* u, int j, Dual<T>* ud) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) ud[k] = Dual<T>(u[k], k == j ? T(1) : T(0));
+}
+
+// stress cotangent ls (6) -> state and mu0 cotangents, through the exact tangent
+template <class T>
+__device__ inline void stress_vjp(const T* u, const MatP<T>& m, const Law<T>& law, const T ls[6],
+                                  T gu[10], T& gmu) {
+  T ds[6][7];
+  cdm_tangent(u, m, law, ds);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s += ls[k] * ds[k][q];
+    gu[q] += s;
+  }
+  T sa = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sa += ls[k] * ds[k][6];
+  gu[9] += sa;
+  // d sigma_k / d mu0 = 2 eps_k
+  T sm = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sm += ls[k] * T(2) * u[k];
+  gmu += sm;
+}
+
+// w^T d(F_n)/du for the normal flux F_n = n_d F^d(u)
+template <class T>
+__device__ inline void normal_flux_vjp(const T* u, const T n[3], const MatP<T>& m,
+                                       const Law<T>& law, const T w[10], T gu[10], T& gmu) {
+  gu[6] += -w[0] * n[0] - T(0.5) * w[3] * n[1] - T(0.5) * w[5] * n[2];
+  gu[7] += -w[1] * n[1] - T(0.5) * w[3] * n[0] - T(0.5) * w[4] * n[2];
+  gu[8] += -w[2] * n[2] - T(0.5) * w[4] * n[1] - T(0.5) * w[5] * n[0];
+  const T ir = T(1) / m.rho;
+  T ls[6];
+  ls[0] = -ir * n[0] * w[6];
+  ls[1] = -ir * n[1] * w[7];
+  ls[2] = -ir * n[2] * w[8];
+  ls[3] = -ir * (n[1] * w[6] + n[0] * w[7]);   // sigma_xy appears in rows x (n_y) and y (n_x)
+  ls[4] = -ir * (n[2] * w[7] + n[1] * w[8]);
+  ls[5] = -ir * (n[0] * w[8] + n[2] * w[6]);
+  stress_vjp(u, m, law, ls, gu, gmu);
+}
+
+// c = sqrt(lambda_max(rho Q)/rho) and its derivatives with respect to the
+// state (10) and mu0
+template <class T>
+__device__ inline T llf_speed_grad(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law,
+                                   T dc[10], T& dcmu) {
+  T Q[3][3];
+  acoustic_rhoQ(u, n, m, law, Q);
+  const T lam = sym3_lmax(Q[0][0], Q[1][1], Q[2][2], Q[0][1], Q[0][2], Q[1][2]);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) dc[k] = T(0);
+  dcmu = T(0);
+  const T lm = lam / m.rho;
+  if (!(lm > T(0))) return T(0);
+  const T c = sqrt(lm);
+  // eigenvector of lambda_max: largest cross product of two rows of
+  // (Q - lambda I)/lambda (scaled to O(1): squared cross products of the
+  // unscaled rows, ~ Q^4 ~ 1e44, overflow FP32)
+  const T il = T(1) / lam;
+  const T r[3][3] = {{(Q[0][0] - lam) * il, Q[0][1] * il, Q[0][2] * il},
+                     {Q[1][0] * il, (Q[1][1] - lam) * il, Q[1][2] * il},
+                     {Q[2][0] * il, Q[2][1] * il, (Q[2][2] - lam) * il}};
+  T v[3] = {T(0), T(0), T(0)};
+  T best = T(-1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3;
+    const T x = r[a][1] * r[b][2] - r[a][2] * r[b][1];
+    const T y = r[a][2] * r[b][0] - r[a][0] * r[b][2];
+    const T z = r[a][0] * r[b][1] - r[a][1] * r[b][0];
+    const T nn = x * x + y * y + z * z;
+    if (nn > best) {
+      best = nn;
+      v[0] = x;
+      v[1] = y;
+      v[2] = z;
+    }
+  }
+  if (!(best > T(0))) return c;
+  const T iv = T(1) / sqrt(best);
+  v[0] *= iv;
+  v[1] *= iv;
+  v[2] *= iv;
+  // d lambda = v^T dQ v; c = sqrt(lambda/rho): dc = d lambda / (2 c rho)
+  const T f = T(1) / (T(2) * c * m.rho);
+  const MatP<Dual<T>> md0 = dual_mat(m, false);
+  const Law<Dual<T>> ld = dual_law(law);
+  Dual<T> ud[10];
+  Dual<T> nd[3] = {Dual<T>(n[0], T(0)), Dual<T>(n[1], T(0)), Dual<T>(n[2], T(0))};
+  Dual<T> Qd[3][3];
+  for (int j = 0; j < 11; ++j) {
+    if (j >= 6 && j < 9) continue;              // velocities do not enter Q
+    dual_state(u, j, ud);
+    const MatP<Dual<T>> md = j == 10 ? dual_mat(m, true) : md0;
+    acoustic_rhoQ(ud, nd, md, ld, Qd);
+    T dl = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) dl += v[a] * Qd[a][b].d * v[b];
+    if (j == 10)
+      dcmu = dl * f;
+    else
+      dc[j] = dl * f;
+  }
+  return c;
+}
+
+// LLF flux F* = (F_n(u-) + F_n(u+))/2 + C (u- - u+)/2: cotangents of u- and of
+// the minus-side mu0 for the flux cotangent w
+template <class T>
+__device__ inline void llf_vjp_minus(const T* um, const T* up, const T n[3], const MatP<T>& mm,
+                                     const MatP<T>& mp, const Law<T>& law, const T w[10],
+                                     T gu[10], T& gmu) {
+  T wh[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) wh[k] = T(0.5) * w[k];
+  normal_flux_vjp(um, n, mm, law, wh, gu, gmu);
+  T ub[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) ub[k] = T(0.5) * (um[k] + up[k]);
+  T d1[10], d2[10], m1, m2;
+  const T c1 = llf_speed_grad(ub, n, mm, law, d1, m1);
+  const T c2 = llf_speed_grad(ub, n, mp, law, d2, m2);
+  // tie rule: each side takes one half
+  const T a1 = c1 > c2 ? T(1) : (c1 < c2 ? T(0) : T(0.5));
+  const T a2 = T(1) - a1;
+  const T C = c1 > c2 ? c1 : c2;
+  T jump = T(0);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) jump += w[k] * (um[k] - up[k]);
+  // d/du-: C w/2 + (w . jump)/2 * dC/dubar * 1/2
+#pragma unroll
+  for (int k = 0; k < 10; ++k)
+    gu[k] += T(0.5) * C * w[k] + T(0.25) * jump * (a1 * d1[k] + a2 * d2[k]);
+  gmu += T(0.5) * jump * a1 * m1;
+}
+
+// boundary flux cotangents by forward-mode dual numbers
+template <class T>
+__device__ inline void boundary_vjp(int kind, const T* u, const T n[3], const MatP<T>& m,
+                                    const Law<T>& law, const T w[10], T gu[10], T& gmu) {
+  const Law<Dual<T>> ld = dual_law(law);
+  const MatP<Dual<T>> md0 = dual_mat(m, false);
+  Dual<T> nd[3] = {Dual<T>(n[0], T(0)), Dual<T>(n[1], T(0)), Dual<T>(n[2], T(0))};
+  Dual<T> ud[10], F[10];
+  // j = 0..9 seeds one state entry (alpha enters through the clamped moduli);
+  // j = 10 seeds mu0
+  for (int j = 0; j < 11; ++j) {
+    dual_state(u, j, ud);
+    const MatP<Dual<T>> md = j == 10 ? dual_mat(m, true) : md0;
+    boundary_flux(kind, ud, nd, md, ld, F);
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) s += w[k] * F[k].d;
+    if (j == 10)
+      gmu += s;
+    else
+      gu[j] += s;
+  }
+}
+
+// damage rate r = C_d gamma_r I2 (xi - xi0): state and C_d cotangents for the
+// rate cotangent lr
+template <class T>
+__device__ inline void rate_vjp(const T* u, const MatP<T>& m, const Law<T>& law, T lr, T gu[10],
+                                T& gcd) {
+  Parts<T> p = cdm_parts(u, law);
+  if (p.guard || !(p.xi > m.xi0)) return;
+  // r = C_d gamma_r (I1 s - xi0 I2),  ds/du_q = w_q u_q / s
+  const T k = lr * m.cd * m.gr;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const T wq = q < 3 ? T(1) : T(2);
+    gu[q] += k * ((q < 3 ? p.s : T(0)) + p.I1 * wq * u[q] / p.s - T(2) * m.xi0 * wq * u[q]);
+  }
+  gcd += lr * m.gr * p.I2 * (p.xi - m.xi0);
+}
+
+// tangent cotangent lt (6 x 7, the cell-average weight folded in): state
+// cotangent through the second derivatives of the stress (dual numbers)
+template <class T>
+__device__ inline void tangent_vjp(const T* u, const MatP<T>& m, const Law<T>& law,
+                                   const T lt[6][7], T gu[10]) {
+  const Law<Dual<T>> ld = dual_law(law);
+  const MatP<Dual<T>> md = dual_mat(m, false);
+  Dual<T> ud[10];
+  Dual<T> ds[6][7];
+  for (int j = 0; j < 10; ++j) {
+    if (j >= 6 && j < 9) continue;              // velocities do not enter the tangent
+    dual_state(u, j, ud);
+    cdm_tangent(ud, md, ld, ds);
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) s += lt[k][c] * ds[k][c].d;
+    gu[j] += s;
+  }
+}
+
+}  // namespace dgd

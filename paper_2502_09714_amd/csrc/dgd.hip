@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/dgd.h"
+#include "adjoint_kernels.hpp"
 #include "kernels.hpp"
 #include "refgen.hpp"
 
@@ -42,7 +43,7 @@ struct dgd_handle {
   RefData ref;
   size_t tsize = 8;  // bytes of the working type
   // reference data on the device
-  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Wpk, Vd, wqd, Pwd;
+  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Wpk, Vd, wqd, Pwd, betad;
   int kpl = 0;  // padded mode count of the time-point state layout
   double inv_wsum = 6.0, phi0_mean = 0.0;
   // mesh and material
@@ -63,15 +64,26 @@ struct dgd_handle {
   DevBuf r_elem, r_phi, seis;
   long long nrec_steps = 0, seis_cap = 0;
   // profiling: event pairs per kernel class
+  // discrete adjoint: transposed reference data, adjoint state, checkpoints
+  DevBuf VTpk, STpk, PTpk, KTpk;
+  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, save9, savea;
+  std::vector<DevBuf> ck9, cka;
+  std::vector<double> ck_t;
+  long long tape_steps = 0, tape_every = 0, tape_seis0 = 0;
+  bool tape = false;
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 
   ~dgd_handle() {
-    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Wpk, &Vd, &wqd, &Pwd, &geo, &fgeo,
+    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Wpk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
                      &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
-                     &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis};
+                     &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
+                     &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
+                     &adjWa, &dlds, &seg9, &sega, &save9, &savea};
     for (DevBuf* b : all) b->release();
+    for (DevBuf& b : ck9) b.release();
+    for (DevBuf& b : cka) b.release();
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
       (void)hipEventDestroy(u.second.second);
@@ -213,6 +225,41 @@ dgd_status build_packed(dgd_handle* h) {
       (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)) ||
       (st = upload(h, h->Wpk, wp)))
     return st;
+  if constexpr (P != PREC_BF16) {
+    // transposed operators of the discrete adjoint
+    std::vector<AF> vt, stt, pt, kt;
+    for (int c = 0; c < DM::NCH; ++c) {
+      append(vt, pack_A<P>(
+                     [&](int m, int kk) {
+                       int q = 64 * c + kk;
+                       return (m < L && q < Q) ? r.V[(size_t)q * L + m] : 0.0;
+                     },
+                     DM::MT, 64 / KS));
+      append(pt, pack_A<P>(
+                     [&](int m, int kk) {
+                       int q = 64 * c + m;
+                       return (q < Q && kk < L) ? r.Pw[(size_t)kk * Q + q] : 0.0;
+                     },
+                     4, KSL));
+    }
+    for (int e = 0; e < 3; ++e) {
+      for (int c = 0; c < DM::NCH; ++c)
+        append(stt, pack_A<P>(
+                        [&](int m, int kk) {
+                          int q = 64 * c + m;
+                          return (q < Q && kk < L) ? r.Sw[((size_t)e * L + kk) * Q + q] : 0.0;
+                        },
+                        4, KSL));
+      append(kt, pack_A<P>(
+                     [&](int m, int kk) {
+                       return (m < L && kk < L) ? r.K[((size_t)e * L + kk) * L + m] : 0.0;
+                     },
+                     DM::MT, KSL));
+    }
+    if ((st = upload(h, h->VTpk, vt)) || (st = upload(h, h->STpk, stt)) ||
+        (st = upload(h, h->PTpk, pt)) || (st = upload(h, h->KTpk, kt)))
+      return st;
+  }
   h->kpl = KPL;
   (void)sizeof(T);
   return DGD_OK;
@@ -345,6 +392,99 @@ template <int N, int P> struct BuildFn {
 template <int N, int P> struct StepFn {
   static dgd_status run(dgd_handle* h, long long n) { return step_impl<N, P>(h, n); }
 };
+
+// ---------------------------------------------------------------- discrete adjoint
+size_t lam_elems(const dgd_handle* h) { return (size_t)h->ne * h->kpl * 16; }
+
+dgd_status alloc_adjoint(dgd_handle* h) {
+  const size_t E = (size_t)h->ne, L = h->ref.L;
+  dgd_status s;
+  if ((s = dalloc(h, h->lam[0], lam_elems(h) * h->tsize)) ||
+      (s = dalloc(h, h->lam[1], lam_elems(h) * h->tsize)) ||
+      (s = dalloc(h, h->lzf, lam_elems(h) * h->ref.Nt * h->tsize)) ||
+      (s = dalloc(h, h->gmu, E * sizeof(double))) || (s = dalloc(h, h->gcd, E * sizeof(double))) ||
+      (s = dalloc(h, h->adjW9, E * 9 * L * h->tsize)) ||
+      (s = dalloc(h, h->adjWa, E * L * sizeof(double))))
+    return s;
+  HIPCHK(h, hipMemsetAsync(h->gmu.p, 0, E * sizeof(double), h->stream));
+  HIPCHK(h, hipMemsetAsync(h->gcd.p, 0, E * sizeof(double), h->stream));
+  return DGD_OK;
+}
+
+// lambda_out = (d step / d U^n)^T lambda_in at the state (U9, Ua); adds the
+// material cotangents of this step to gmu, gcd
+template <int N, int P>
+dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, const void* lam_in,
+                             void* lam_out) {
+  using T = typename Prec<P>::T;
+  using AF = typename Prec<P>::AF;
+  if constexpr (P == PREC_BF16) {
+    return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  } else {
+    const long long per = (h->ne + 7) / 8;
+    const dim3 grid((unsigned)(8 * per)), block(64);
+    StepArgs<P> a = make_args<N, P>(h);
+    a.U9 = (const T*)U9;
+    a.Ua = Ua;
+    a.W9 = (T*)h->adjW9.p;
+    a.Wa = (double*)h->adjWa.p;
+    AdjArgs<P> A;
+    A.s = a;
+    A.lam = (const T*)lam_in;
+    A.lamOut = (T*)lam_out;
+    A.lzf = (T*)h->lzf.p;
+    A.VTpk = (const AF*)h->VTpk.p;
+    A.STpk = (const AF*)h->STpk.p;
+    A.PTpk = (const AF*)h->PTpk.p;
+    A.KTpk = (const AF*)h->KTpk.p;
+    A.wq = (const double*)h->wqd.p;
+    A.beta = (const double*)h->betad.p;
+    A.gmu = (double*)h->gmu.p;
+    A.gcd = (double*)h->gcd.p;
+    timed(h, 4, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
+    timed(h, 5, [&] { hipLaunchKernelGGL((k_adj_face<N, P>), grid, block, 0, h->stream, A); });
+    timed(h, 6, [&] { hipLaunchKernelGGL((k_adj_volume<N, P>), grid, block, 0, h->stream, A); });
+    HIPCHK(h, hipGetLastError());
+    return DGD_OK;
+  }
+}
+
+template <int N, int P> struct AdjStepFn {
+  static dgd_status run(dgd_handle* h, const void* U9, const double* Ua, const void* li, void* lo) {
+    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo);
+  }
+};
+
+template <class T>
+void launch_lam_from_f64(dgd_handle* h, const double* src, void* lam) {
+  const long long n = (long long)lam_elems(h);
+  hipLaunchKernelGGL((k_lam_from_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     h->stream, h->ne, h->ref.L, h->kpl, src, (T*)lam);
+}
+
+template <class T>
+void launch_lam_to_f64(dgd_handle* h, const void* lam, double* dst) {
+  const long long n = h->ne * 10 * h->ref.L;
+  hipLaunchKernelGGL((k_lam_to_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                     h->ne, h->ref.L, h->kpl, (const T*)lam, dst);
+}
+
+void release_tape(dgd_handle* h) {
+  for (DevBuf& b : h->ck9) b.release();
+  for (DevBuf& b : h->cka) b.release();
+  h->ck9.clear();
+  h->cka.clear();
+  h->ck_t.clear();
+  h->tape = false;
+  h->tape_steps = h->tape_every = 0;
+}
+
+dgd_status copy_state(dgd_handle* h, void* d9, void* da, const void* s9, const void* sa) {
+  const size_t E = (size_t)h->ne, L = h->ref.L;
+  HIPCHK(h, hipMemcpyAsync(d9, s9, E * 9 * L * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(da, sa, E * L * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return DGD_OK;
+}
 
 // ---------------------------------------------------------------- mesh helpers
 const int kFV[4][3] = {{0, 2, 1}, {0, 1, 3}, {0, 3, 2}, {1, 2, 3}};
@@ -486,6 +626,7 @@ dgd_status dgd_create(int N, int precision, void* hip_stream, dgd_handle** out) 
   if (s == DGD_OK) s = upload(h, h->Vd, h->ref.V);
   if (s == DGD_OK) s = upload(h, h->wqd, h->ref.wq);
   if (s == DGD_OK) s = upload(h, h->Pwd, h->ref.Pw);
+  if (s == DGD_OK) s = upload(h, h->betad, h->ref.beta);
   if (s != DGD_OK) {
     delete h;
     return s;
@@ -933,7 +1074,7 @@ dgd_status dgd_set_profiling(dgd_handle* h, int on) {
 dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms, int64_t* launches) {
   if (!h || !ms || !launches) return DGD_EINVAL;
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < DGD_NUM_KERNEL_CLASSES; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
   }
@@ -970,6 +1111,170 @@ dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
       for (size_t p = 0; p < 10; ++p)
         for (size_t l = 0; l < L; ++l)
           out[((e * Nt + z) * 10 + p) * L + l] = tmp[((e * Nt + z) * K + l) * 16 + p];
+  return DGD_OK;
+}
+
+dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_out,
+                            double* grad_mu0, double* grad_cd) {
+  if (!h || !lam_next || !lam_out) return DGD_EINVAL;
+  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
+    return fail(h, DGD_ESTATE, "mesh, material, params and state are needed");
+  dgd_status s = alloc_adjoint(h);
+  if (s) return s;
+  const size_t n = (size_t)h->ne * 10 * h->ref.L;
+  if ((s = dalloc(h, h->scratch, n * sizeof(double)))) return s;
+  HIPCHK(h, hipMemcpyAsync(h->scratch.p, lam_next, n * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+  if (h->prec == DGD_FP64)
+    launch_lam_from_f64<double>(h, (const double*)h->scratch.p, h->lam[0].p);
+  else
+    launch_lam_from_f64<float>(h, (const double*)h->scratch.p, h->lam[0].p);
+  HIPCHK(h, hipGetLastError());
+  if ((s = dispatch<AdjStepFn>(h, (const void*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                               (const void*)h->lam[0].p, h->lam[1].p)))
+    return s;
+  if (h->prec == DGD_FP64)
+    launch_lam_to_f64<double>(h, h->lam[1].p, (double*)h->scratch.p);
+  else
+    launch_lam_to_f64<float>(h, h->lam[1].p, (double*)h->scratch.p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(lam_out, h->scratch.p, n * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+  if (grad_mu0)
+    HIPCHK(h, hipMemcpyAsync(grad_mu0, h->gmu.p, (size_t)h->ne * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  if (grad_cd)
+    HIPCHK(h, hipMemcpyAsync(grad_cd, h->gcd.p, (size_t)h->ne * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->scratch.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every) {
+  if (!h) return DGD_EINVAL;
+  if (nsteps < 1 || every < 1) return fail(h, DGD_EINVAL, "nsteps >= 1 and every >= 1 needed");
+  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
+    return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
+  release_tape(h);
+  dgd_status s = ensure_seis(h, nsteps);
+  if (s) return s;
+  const size_t E = (size_t)h->ne, L = h->ref.L;
+  const long long nck = (nsteps + every - 1) / every;
+  h->ck9.resize(nck);
+  h->cka.resize(nck);
+  h->ck_t.resize(nck);
+  h->tape_seis0 = h->nrec_steps;
+  for (long long c = 0; c < nck; ++c) {
+    if ((s = dalloc(h, h->ck9[c], E * 9 * L * h->tsize)) ||
+        (s = dalloc(h, h->cka[c], E * L * sizeof(double)))) {
+      release_tape(h);
+      return s;
+    }
+    if ((s = copy_state(h, h->ck9[c].p, h->cka[c].p, h->U9[h->cur].p, h->Ua[h->cur].p))) return s;
+    h->ck_t[c] = h->t;
+    const long long chunk = std::min<long long>(every, nsteps - c * every);
+    if ((s = dispatch<StepFn>(h, chunk))) return s;
+  }
+  if ((s = dgd_synchronize(h))) return s;
+  h->tape = true;
+  h->tape_steps = nsteps;
+  h->tape_every = every;
+  return DGD_OK;
+}
+
+dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0, double* grad_cd,
+                        double* grad_u0) {
+  if (!h) return DGD_EINVAL;
+  if (!h->tape) return fail(h, DGD_ESTATE, "no checkpointed forward run to differentiate");
+  if (h->nrec > 0 && !dl_dseis) return fail(h, DGD_EINVAL, "null seismogram cotangent");
+  if (!grad_mu0 || !grad_cd) return fail(h, DGD_EINVAL, "null gradient output");
+  const size_t E = (size_t)h->ne, L = h->ref.L;
+  const long long nsteps = h->tape_steps, every = h->tape_every;
+  const int nrec = h->nrec;
+  dgd_status s = alloc_adjoint(h);
+  if (s) return s;
+  if ((s = dalloc(h, h->save9, E * 9 * L * h->tsize)) ||
+      (s = dalloc(h, h->savea, E * L * sizeof(double))) ||
+      (s = dalloc(h, h->seg9, (size_t)every * E * 9 * L * h->tsize)) ||
+      (s = dalloc(h, h->sega, (size_t)every * E * L * sizeof(double))))
+    return s;
+  if (nrec > 0) {
+    if ((s = dalloc(h, h->dlds, (size_t)nsteps * nrec * 3 * sizeof(double)))) return s;
+    HIPCHK(h, hipMemcpyAsync(h->dlds.p, dl_dseis, (size_t)nsteps * nrec * 3 * sizeof(double),
+                             hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(h, hipMemsetAsync(h->lam[0].p, 0, lam_elems(h) * h->tsize, h->stream));
+  if ((s = copy_state(h, h->save9.p, h->savea.p, h->U9[h->cur].p, h->Ua[h->cur].p))) return s;
+  const double t_save = h->t;
+  const bool prof = h->profiling;
+  int lc = 0;
+  h->nrec = 0;   // the replay records nothing
+  const long long nck = (long long)h->ck9.size();
+  for (long long c = nck - 1; c >= 0 && s == DGD_OK; --c) {
+    const long long j0 = c * every, j1 = std::min<long long>(j0 + every, nsteps);
+    if ((s = copy_state(h, h->U9[h->cur].p, h->Ua[h->cur].p, h->ck9[c].p, h->cka[c].p))) break;
+    h->t = h->ck_t[c];
+    h->profiling = false;
+    for (long long j = j0; j < j1 && s == DGD_OK; ++j) {
+      char* d9 = (char*)h->seg9.p + (size_t)(j - j0) * E * 9 * L * h->tsize;
+      char* da = (char*)h->sega.p + (size_t)(j - j0) * E * L * sizeof(double);
+      if ((s = copy_state(h, d9, da, h->U9[h->cur].p, h->Ua[h->cur].p))) break;
+      if (j + 1 < j1) s = dispatch<StepFn>(h, 1);
+    }
+    h->profiling = prof;
+    for (long long j = j1 - 1; j >= j0 && s == DGD_OK; --j) {
+      if (nrec > 0) {
+        const double* g = (const double*)h->dlds.p + (size_t)j * nrec * 3;
+        timed(h, 7, [&] {
+          if (h->prec == DGD_FP64)
+            hipLaunchKernelGGL((k_adj_receivers<double>), dim3(1), dim3(3 * L), 0, h->stream, nrec,
+                               (int)L, h->kpl, (const long long*)h->r_elem.p,
+                               (const double*)h->r_phi.p, g, (double*)h->lam[lc].p);
+          else
+            hipLaunchKernelGGL((k_adj_receivers<float>), dim3(1), dim3(3 * L), 0, h->stream, nrec,
+                               (int)L, h->kpl, (const long long*)h->r_elem.p,
+                               (const double*)h->r_phi.p, g, (float*)h->lam[lc].p);
+        });
+      }
+      const char* u9 = (const char*)h->seg9.p + (size_t)(j - j0) * E * 9 * L * h->tsize;
+      const double* ua = (const double*)((const char*)h->sega.p + (size_t)(j - j0) * E * L * sizeof(double));
+      s = dispatch<AdjStepFn>(h, (const void*)u9, ua, (const void*)h->lam[lc].p, h->lam[1 - lc].p);
+      lc = 1 - lc;
+    }
+  }
+  h->nrec = nrec;
+  h->profiling = prof;
+  const dgd_status s2 = copy_state(h, h->U9[h->cur].p, h->Ua[h->cur].p, h->save9.p, h->savea.p);
+  h->t = t_save;
+  if (s) return s;
+  if (s2) return s2;
+  HIPCHK(h, hipMemcpyAsync(grad_mu0, h->gmu.p, E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad_cd, h->gcd.p, E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (grad_u0) {
+    const size_t n = E * 10 * L;
+    if ((s = dalloc(h, h->scratch, n * sizeof(double)))) return s;
+    if (h->prec == DGD_FP64)
+      launch_lam_to_f64<double>(h, h->lam[lc].p, (double*)h->scratch.p);
+    else
+      launch_lam_to_f64<float>(h, h->lam[lc].p, (double*)h->scratch.p);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(grad_u0, h->scratch.p, n * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->scratch.release();
+  h->seg9.release();
+  h->sega.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_release_tape(dgd_handle* h) {
+  if (!h) return DGD_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  release_tape(h);
   return DGD_OK;
 }
 

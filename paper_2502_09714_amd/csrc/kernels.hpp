@@ -93,54 +93,57 @@ __device__ inline T wave_sum(T v) {
 __device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
 __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
+// LDS working set of the predictor of one element (one wavefront)
+template <int N, int P> struct PredLDS {
+  using T = typename Prec<P>::T;
+  static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
+  static constexpr int KPL = round_up(L, Prec<P>::KS);
+  static constexpr int BIG = 64 * 16 > 3 * KPL * 16 ? 64 * 16 : 3 * KPL * 16;
+  T D[N + 1][KPL * 16];   // D^0 = U^n, D^1..D^N time derivatives, [l][16] layout
+  T W[KPL * 16];          // time-point state / scratch
+  T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
+  T A[300];               // A*_e (3 x 10 x 10)
+  T R[NCH * 64];          // nodal damage rate at t_n
+  T Acc[48];              // cell-averaged tangent (6 x 7)
+  T J[9];                 // Theta^-1
+};
+
+// Prediction (Appendix A.1): load U^n, cell-averaged tangent, A*_e, damage
+// source at t_n, Cauchy-Kovalevskaya recursion.  Leaves D^0..D^N in S.D.
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
+__device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P>& S,
+                                       const MatP<typename Prec<P>::T>& m, int lane) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
   constexpr int PA_ = Accurate<P>::value;
   using PA = Prec<PA_>;
   using DM = Dims<N>;
-  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int L = DM::L, Q = DM::Q, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
-  constexpr int BIG = 64 * 16 > 3 * KPL * 16 ? 64 * 16 : 3 * KPL * 16;
-  __shared__ T sD[N + 1][KPL * 16];
-  __shared__ T sW[KPL * 16];
-  // one buffer for: nodal values / tangent blocks / volume integrands of a
-  // 64-point chunk, and the right-hand sides of the CK recursion
-  __shared__ T sB[BIG];
-  T* const sX = sB;
-  __shared__ T sA[300];
-  __shared__ T sR[NCH * 64];
-  __shared__ T sAcc[48];
-  __shared__ T sJ[9];
-
-  const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  constexpr int KSQA = 64 / PA::KS;
+  T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
 
-  for (int i = lane; i < (N + 1) * KPL * 16; i += 64) (&sD[0][0])[i] = T(0);
-  for (int i = lane; i < KPL * 16; i += 64) sW[i] = T(0);
+  for (int i = lane; i < (N + 1) * KPL * 16; i += 64) (&S.D[0][0])[i] = T(0);
+  for (int i = lane; i < KPL * 16; i += 64) S.W[i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
     const int p = i / L, l = i - p * L;
-    sD[0][l * 16 + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
+    S.D[0][l * 16 + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
   }
-  const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  if (lane < 9) sJ[lane] = (T)a.geo[e * 16 + lane];
+  if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
 
-  // 1. cell average of the pointwise tangent (weighted sum on the matrix cores)
-  //    and nodal damage rate at t_n
+  // cell average of the pointwise tangent (weighted sum on the matrix cores)
+  // and nodal damage rate at t_n
   typename PA::Acc Cav[3];
   zero_C<PA_, 3>(Cav);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, sD[0], C, lane);
+    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     const int q = 64 * c + lane;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
         for (int j = 0; j < 7; ++j) ds[k][j] = T(0);
     }
-    sR[q] = r;
+    S.R[q] = r;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       __syncthreads();
@@ -178,62 +181,87 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   if (lane < 16) {
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-      if (16 * t + lane < 42) sAcc[16 * t + lane] = Cav[t][0] * a.inv_wsum;
+      if (16 * t + lane < 42) S.Acc[16 * t + lane] = Cav[t][0] * a.inv_wsum;
   }
   __syncthreads();
 
-  // 2. A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each)
+  // A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each)
   for (int i = lane; i < 300; i += 64) {
     const int ee = i / 100, p = (i / 10) % 10, q = i % 10;
     T v = T(0);
     if (p < 6 && q >= 6 && q < 9) {
       const int mm = q - 6, ii = kVI[p], jj = kVJ[p];
-      v = T(-0.5) * ((ii == mm ? sJ[ee * 3 + jj] : T(0)) + (jj == mm ? sJ[ee * 3 + ii] : T(0)));
+      v = T(-0.5) * ((ii == mm ? S.J[ee * 3 + jj] : T(0)) + (jj == mm ? S.J[ee * 3 + ii] : T(0)));
     } else if (p >= 6 && p < 9 && (q < 6 || q == 9)) {
       const int ii = p - 6, col = q < 6 ? q : 6;
       T s = T(0);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) s += sJ[ee * 3 + d] * sAcc[sym_idx(ii, d) * 7 + col];
+      for (int d = 0; d < 3; ++d) s += S.J[ee * 3 + d] * S.Acc[sym_idx(ii, d) * 7 + col];
       v = -s / m.rho;
     }
-    sA[i] = v;
+    S.A[i] = v;
   }
-  // damage source at t_n projected on the modes (lands in column 9 of sW)
+  // damage source at t_n projected on the modes (lands in column 9 of W)
   {
     typename PA::Acc Cs[MT];
     zero_C<PA_, MT>(Cs);
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
-      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Cs, lane);
-    store_C<PA_, MT>(Cs, sW, L, T(1), lane);
+      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R + 64 * c, Cs, lane);
+    store_C<PA_, MT>(Cs, S.W, L, T(1), lane);
   }
   __syncthreads();
 
-  // 3. Cauchy-Kovalevskaya recursion.  The right-hand-side buffer held nodal
+  // Cauchy-Kovalevskaya recursion.  The right-hand-side buffer held nodal
   // values before: clear it so that its padding rows and columns (read by the
   // matrix cores against zero A entries) are zero, not stale values.
-  for (int i = lane; i < 3 * KPL * 16; i += 64) sB[i] = T(0);
+  for (int i = lane; i < 3 * KPL * 16; i += 64) S.B[i] = T(0);
   __syncthreads();
 #pragma unroll
   for (int i = 1; i <= N; ++i) {
     for (int idx = lane; idx < 3 * L * 10; idx += 64) {
       const int ee = idx / (L * 10), r = idx - ee * L * 10, l = r / 10, p = r - l * 10;
-      const T* Ar = sA + ee * 100 + p * 10;
-      const T* Dr = &sD[i - 1][l * 16];
+      const T* Ar = S.A + ee * 100 + p * 10;
+      const T* Dr = &S.D[i - 1][l * 16];
       T s = T(0);
 #pragma unroll
       for (int q = 0; q < 10; ++q) s += Dr[q] * Ar[q];
-      sB[(ee * KPL + l) * 16 + p] = s;
+      S.B[(ee * KPL + l) * 16 + p] = s;
     }
     __syncthreads();
     Acc C[MT];
     zero_C<P, MT>(C);
-    wave_gemm<P, MT, 3 * KSL>(a.Kpk, sB, C, lane);
-    store_C<P, MT>(C, sD[i], L, T(-1), lane);
+    wave_gemm<P, MT, 3 * KSL>(a.Kpk, S.B, C, lane);
+    store_C<P, MT>(C, S.D[i], L, T(-1), lane);
     __syncthreads();
-    if (i == 1 && lane < L) sD[1][lane * 16 + 9] += sW[lane * 16 + 9];
+    if (i == 1 && lane < L) S.D[1][lane * 16 + 9] += S.W[lane * 16 + 9];
     __syncthreads();
   }
+}
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  constexpr int PA_ = Accurate<P>::value;
+  using PA = Prec<PA_>;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  __shared__ PredLDS<N, P> S;
+  T* const sX = S.B;
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  predictor_stage<N, P>(a, e, S, m, lane);
+  auto& sD = S.D;
+  T* const sW = S.W;
+  T* const sR = S.R;
 
   // 4. time points and volume integrands
   T gacc[NCH][27];
@@ -248,7 +276,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   const T ir = T(1) / m.rho;
   T Ji[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Ji[k] = sJ[k];
+  for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
     cz[0] = T(1);

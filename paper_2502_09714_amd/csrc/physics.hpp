@@ -152,27 +152,33 @@ __device__ inline T sym3_lmax(T a00, T a11, T a22, T a01, T a02, T a12) {
   return q + T(2) * p * cos(phi);
 }
 
+// rho * acoustic tensor n . (d sigma / d eps) . n of the CDM law (symmetric)
 template <class T>
-__device__ inline T llf_speed(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law) {
+__device__ inline void acoustic_rhoQ(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law,
+                                     T Q[3][3]) {
   Parts<T> p = cdm_parts(u, law);
   const T agr = p.ac * m.gr;
   const T h = (m.mu + p.ac * m.xi0 * m.gr) - T(0.5) * agr * p.xi;
   // (eps n) of the scaled strain; the eps/sqrt(I2) terms are scale free
   const T im = p.im;
-  const T en0 = (u[0] * n[0] + u[3] * n[1] + u[5] * n[2]) * im;
-  const T en1 = (u[3] * n[0] + u[1] * n[1] + u[4] * n[2]) * im;
-  const T en2 = (u[5] * n[0] + u[4] * n[1] + u[2] * n[2]) * im;
+  const T en[3] = {(u[0] * n[0] + u[3] * n[1] + u[5] * n[2]) * im,
+                   (u[3] * n[0] + u[1] * n[1] + u[4] * n[2]) * im,
+                   (u[5] * n[0] + u[4] * n[1] + u[2] * n[2]) * im};
   const T is = p.guard ? T(0) : T(1) / p.sp;
   const T c1 = agr * is;                       // coefficient of n (eps n) + (eps n) n
   const T c2 = agr * p.I1p * is * is * is;     // coefficient of (eps n)(eps n)
-  const T en[3] = {en0, en1, en2};
-  T Q[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       Q[i][k] = m.lam * n[i] * n[k] + h * ((i == k ? T(1) : T(0)) + n[i] * n[k]) -
                 c1 * (n[i] * en[k] + en[i] * n[k]) + c2 * en[i] * en[k];
+}
+
+template <class T>
+__device__ inline T llf_speed(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law) {
+  T Q[3][3];
+  acoustic_rhoQ(u, n, m, law, Q);
   T lm = sym3_lmax(Q[0][0], Q[1][1], Q[2][2], Q[0][1], Q[0][2], Q[1][2]) / m.rho;
   return lm > T(0) ? sqrt(lm) : T(0);
 }

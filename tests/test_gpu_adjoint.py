@@ -1,0 +1,274 @@
+"""GPU parity of the discrete adjoint (through the C-ABI) against reverse-mode
+automatic differentiation of the FP64 CPU oracle, and against central finite
+differences of the GPU forward run.
+
+Bars: relative L2 1e-8 against the oracle's gradients in FP64; 1e-4 against
+central differences (step 1e-5 relative); 1e-5 for the FP32 adjoint, on states
+with no point near zero strain (see _smooth_state).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import diff_from_workload, misfit_gradient, step_vjp
+from workloads import make_workload
+from workloads.configs import perturbed_material
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2502_09714_amd import api
+    return api
+
+
+def _to_lib(U):
+    return U.permute(0, 2, 1).contiguous().numpy()
+
+
+def _to_oracle(a):
+    return torch.as_tensor(np.ascontiguousarray(np.transpose(a, (0, 2, 1))))
+
+
+def rl2(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    d = np.linalg.norm(want)
+    return np.linalg.norm(got - want) / d if d > 0 else np.linalg.norm(got)
+
+
+STEP_CASES = [
+    ("c2", dict(n=3, N=2)),                  # free top, absorbing sides, damage growth
+    ("c1", dict(n=3, N=1)),                  # periodic plane wave, no damage growth
+    ("c3", dict(n=3, N=3)),                  # lognormal moduli, degree 3
+    ("c2", dict(n=3, N=4)),                  # two 64-point chunks
+]
+
+
+def _state_after(S, w, k):
+    U = S.project(w.ic)
+    with torch.no_grad():
+        for _ in range(k):
+            U = S.step(U)
+    return U.detach()
+
+
+@pytest.mark.parametrize("name,kw", STEP_CASES)
+def test_adjoint_step_fp64(name, kw):
+    w = make_workload(name, **kw)
+    S = diff_from_workload(w)
+    U = _state_after(S, w, 1)           # velocities and damage already moving
+    g = torch.Generator().manual_seed(7)
+    lam = torch.randn(U.shape, dtype=torch.float64, generator=g)
+    want_u, want_mu, want_cd = step_vjp(S, U, lam)
+    sim = _api().from_workload(w, "fp64", state=False)
+    sim.set_state(_to_lib(U))
+    got_u, got_mu, got_cd = sim.adjoint_step(_to_lib(lam))
+    assert rl2(got_u, _to_lib(want_u)) < 1e-8
+    assert rl2(got_mu, want_mu.numpy()) < 1e-8
+    if float(want_cd.abs().max()) > 0:
+        assert rl2(got_cd, want_cd.numpy()) < 1e-8
+    else:
+        assert np.abs(got_cd).max() == 0.0
+    # the state is left as it was
+    assert np.array_equal(sim.get_state(), _to_lib(U))
+    sim.close()
+
+
+def _smooth_state(S, w, seed):
+    """One oracle step from the projected initial condition plus a random
+    background strain and velocity on every mode, so that no point sits near
+    zero strain.  There the law's sqrt(I2) term has a cone point: its second
+    derivative grows like 1/|eps|, and the tangent's derivative taken in FP32
+    at points of nearly zero strain is dominated by rounding."""
+    U = S.project(w.ic).detach()
+    bg = torch.randn(U.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(seed))
+    bg[..., :6] *= 1e-5
+    bg[..., 6:9] *= 1e-3
+    bg[..., 9] = 0.0
+    with torch.no_grad():
+        return S.step(U + bg)
+
+
+def test_adjoint_step_fp32():
+    w = make_workload("c2", n=3, N=2)
+    S = diff_from_workload(w)
+    U = _smooth_state(S, w, 21)
+    lam = torch.randn(U.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(3))
+    want_u, want_mu, want_cd = step_vjp(S, U, lam)
+    sim = _api().from_workload(w, "fp32", state=False)
+    sim.set_state(_to_lib(U))
+    got_u, got_mu, got_cd = sim.adjoint_step(_to_lib(lam))
+    L = _to_lib(lam)
+    assert rl2(got_u - L, _to_lib(want_u) - L) < 1e-5
+    assert rl2(got_mu, want_mu.numpy()) < 1e-5
+    assert rl2(got_cd, want_cd.numpy()) < 1e-5
+    sim.close()
+
+
+def test_misfit_gradient_fp32():
+    w = make_workload("c2", n=3, N=2)
+    S = diff_from_workload(w)
+    U0 = _smooth_state(S, w, 22)
+    m = w.mesh
+    cent = m["xyz"][m["tets"][[5, 40, 77, 120]]].mean(axis=1)
+    nsteps = 4
+    dl = torch.randn((nsteps, 4, 3), dtype=torch.float64, generator=torch.Generator().manual_seed(6))
+    want_mu, want_cd, want_u0, _ = misfit_gradient(S, U0, nsteps, dl, receivers=cent)
+    sim = _api().from_workload(w, "fp32", state=False)
+    sim.set_receivers(cent)
+    sim.set_state(_to_lib(U0))
+    sim.forward_checkpointed(nsteps, 3)
+    gmu, gcd, gu0 = sim.backward(dl.numpy(), want_u0=True)
+    assert rl2(gmu, want_mu.numpy()) < 1e-5
+    assert rl2(gcd, want_cd.numpy()) < 1e-5
+    assert rl2(gu0, _to_lib(want_u0)) < 1e-5
+    sim.close()
+
+
+def _misfit_setup():
+    """c4-type run (double-couple point source, 2 Hz Ricker) on a small mesh
+    with receivers near the source; mu0 perturbed by 5 % per element so that
+    neighbours differ (the Lax-Friedrichs speed is then one side's, not a tie)."""
+    w = make_workload("c4", n=4, N=2)
+    w.material = perturbed_material(w.material, seed=4)
+    xs = w.sources["xyz"][0]
+    recx = xs[None, :] + np.array([[310.0, -170.0, 90.0], [-1450.0, 620.0, -330.0],
+                                   [40.0, 35.0, -25.0]])
+    return w, recx
+
+
+def test_misfit_gradient_checkpointed():
+    w, recx = _misfit_setup()
+    nsteps, every, t0 = 5, 2, 0.45       # three segments, the last one ragged
+    S = diff_from_workload(w)
+    U0 = S.project(w.ic).detach()
+    g = torch.Generator().manual_seed(11)
+    dl = torch.randn((nsteps, recx.shape[0], 3), dtype=torch.float64, generator=g)
+    want_mu, want_cd, want_u0, want_seis = misfit_gradient(
+        S, U0, nsteps, dl, t0=t0, sources=w.sources, receivers=recx)
+    sim = _api().from_workload(w, "fp64", state=False)
+    sim.set_receivers(recx)
+    sim.set_state(_to_lib(U0))
+    sim.set_time(t0)
+    sim.forward_checkpointed(nsteps, every)
+    seis = sim.get_seismograms()
+    assert rl2(seis, want_seis.numpy()) < 1e-10
+    final = sim.get_state()
+    gmu, gcd, gu0 = sim.backward(dl.numpy(), want_u0=True)
+    assert rl2(gmu, want_mu.numpy()) < 1e-8
+    assert rl2(gu0, _to_lib(want_u0)) < 1e-8
+    assert np.abs(gcd).max() == 0.0 or rl2(gcd, want_cd.numpy()) < 1e-8
+    # forward state, time and seismograms untouched by the backward sweep
+    assert np.array_equal(sim.get_state(), final)
+    assert abs(sim.get_time() - (t0 + nsteps * w.dt)) < 1e-12
+    assert np.array_equal(sim.get_seismograms(), seis)
+    # a second backward with the same tape gives the same gradient
+    gmu2, gcd2 = sim.backward(dl.numpy())
+    assert np.array_equal(gmu2, gmu) and np.array_equal(gcd2, gcd)
+    sim.close()
+
+
+def test_damage_gradient_checkpointed():
+    """C_d gradient through several steps of damage growth (c2 recipe)."""
+    w = make_workload("c2", n=3, N=2)
+    S = diff_from_workload(w)
+    U0 = S.project(w.ic).detach()
+    nsteps, every = 4, 3
+    # receivers: the centroids of a few elements
+    m = w.mesh
+    cent = m["xyz"][m["tets"][[5, 40, 77, 120]]].mean(axis=1)
+    dl = torch.randn((nsteps, 4, 3), dtype=torch.float64, generator=torch.Generator().manual_seed(5))
+    want_mu, want_cd, want_u0, _ = misfit_gradient(S, U0, nsteps, dl, receivers=cent)
+    sim = _api().from_workload(w, "fp64", state=False)
+    sim.set_receivers(cent)
+    sim.set_state(_to_lib(U0))
+    sim.forward_checkpointed(nsteps, every)
+    gmu, gcd, gu0 = sim.backward(dl.numpy(), want_u0=True)
+    assert float(want_cd.abs().max()) > 0
+    assert rl2(gmu, want_mu.numpy()) < 1e-8
+    assert rl2(gcd, want_cd.numpy()) < 1e-8
+    assert rl2(gu0, _to_lib(want_u0)) < 1e-8
+    sim.close()
+
+
+def _gpu_misfit(sim, U0, t0, nsteps, dl, material):
+    sim.set_material(**material)
+    sim.set_state(U0)
+    sim.set_time(t0)
+    sim.clear_seismograms()
+    sim.step(nsteps)
+    return float((sim.get_seismograms() * dl).sum())
+
+
+@pytest.mark.parametrize("which", ["mu0", "Cd"])
+def test_gradient_vs_central_differences(which):
+    w = make_workload("c2", n=3, N=2)
+    m = w.mesh
+    cent = m["xyz"][m["tets"][[5, 40, 77, 120]]].mean(axis=1)
+    nsteps = 4
+    sim = _api().from_workload(w, "fp64")
+    sim.set_receivers(cent)
+    U0 = sim.get_state()
+    dl = np.random.default_rng(9).standard_normal((nsteps, 4, 3))
+    sim.forward_checkpointed(nsteps, 2)
+    gmu, gcd = sim.backward(dl)
+    grad = gmu if which == "mu0" else gcd
+    base = {k: np.array(v) for k, v in sim.material.items()}
+    # the three elements with the largest gradients
+    idx = list(np.argsort(-np.abs(grad))[:3])
+    fd, an = [], []
+    for e in idx:
+        h = 1e-5 * base[which][e]
+        mp = {k: v.copy() for k, v in base.items()}
+        mp[which][e] += h
+        Jp = _gpu_misfit(sim, U0, 0.0, nsteps, dl, mp)
+        mp[which][e] -= 2 * h
+        Jm = _gpu_misfit(sim, U0, 0.0, nsteps, dl, mp)
+        fd.append((Jp - Jm) / (2 * h))
+        an.append(grad[e])
+    assert np.abs(an).max() > 0
+    assert rl2(an, fd) < 1e-4, (an, fd)
+    sim.close()
+
+
+def test_autograd_function():
+    from paper_2502_09714_amd.adjoint import seismograms
+    w = make_workload("c2", n=3, N=2)
+    m = w.mesh
+    cent = m["xyz"][m["tets"][[5, 40, 77]]].mean(axis=1)
+    sim = _api().from_workload(w, "fp64")
+    sim.set_receivers(cent)
+    U0 = sim.get_state()
+    mu0 = torch.tensor(w.material["mu0"], requires_grad=True)
+    cd = torch.tensor(w.material["Cd"], requires_grad=True)
+    seis = seismograms(sim, mu0, cd, U0, nsteps=3, every=2)
+    obs = torch.zeros_like(seis)
+    loss = 0.5 * ((seis - obs) ** 2).sum()
+    loss.backward()
+    # same as the direct backward with dL/dseis = seis
+    sim.set_material(**sim.material)
+    sim.set_state(U0)
+    sim.clear_seismograms()
+    sim.forward_checkpointed(3, 3)
+    gmu, gcd = sim.backward(sim.get_seismograms())
+    assert rl2(mu0.grad.numpy(), gmu) < 1e-12
+    assert rl2(cd.grad.numpy(), gcd) < 1e-12
+    sim.close()
+
+
+def test_adjoint_errors():
+    from paper_2502_09714_amd._lib import DGDError
+    w = make_workload("c1", n=3, N=1)
+    sim = _api().from_workload(w, "bf16")
+    with pytest.raises(DGDError):
+        sim.forward_checkpointed(2, 1)
+    with pytest.raises(DGDError):
+        sim.adjoint_step(np.zeros((sim.ne, 10, sim.L)))
+    sim.close()
+    sim = _api().from_workload(w, "fp64")
+    with pytest.raises(DGDError):
+        sim.backward(None)                # no checkpointed run yet
+    with pytest.raises(DGDError):
+        sim.forward_checkpointed(0, 1)
+    sim.close()
