@@ -122,7 +122,13 @@ __device__ inline void normal_flux_vjp(const T* u, const T n[3], const MatP<T>& 
 }
 
 // c = sqrt(lambda_max(rho Q)/rho) and its derivatives with respect to the
-// state (10) and mu0
+// state (10) and mu0.  With v the unit eigenvector of lambda_max, d lambda =
+// v^T d(rho Q) v, and
+//   v^T (rho Q) v = lambda0 (v.n)^2 + h (1 + (v.n)^2) - 2 c1 (v.n) E + c2 E^2,
+//   E = v.(eps n),  h = mu' - a gamma_r xi / 2,  c1 = a gamma_r / s,
+//   c2 = a gamma_r I1 / s^3,
+// differentiated in closed form (the strain terms in scale-free variables;
+// their common factor 1/max|eps| is applied last).
 template <class T>
 __device__ inline T llf_speed_grad(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law,
                                    T dc[10], T& dcmu) {
@@ -163,28 +169,43 @@ __device__ inline T llf_speed_grad(const T* u, const T n[3], const MatP<T>& m, c
   v[0] *= iv;
   v[1] *= iv;
   v[2] *= iv;
-  // d lambda = v^T dQ v; c = sqrt(lambda/rho): dc = d lambda / (2 c rho)
-  const T f = T(1) / (T(2) * c * m.rho);
-  const MatP<Dual<T>> md0 = dual_mat(m, false);
-  const Law<Dual<T>> ld = dual_law(law);
-  Dual<T> ud[10];
-  Dual<T> nd[3] = {Dual<T>(n[0], T(0)), Dual<T>(n[1], T(0)), Dual<T>(n[2], T(0))};
-  Dual<T> Qd[3][3];
-  for (int j = 0; j < 11; ++j) {
-    if (j >= 6 && j < 9) continue;              // velocities do not enter Q
-    dual_state(u, j, ud);
-    const MatP<Dual<T>> md = j == 10 ? dual_mat(m, true) : md0;
-    acoustic_rhoQ(ud, nd, md, ld, Qd);
-    T dl = T(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) dl += v[a] * Qd[a][b].d * v[b];
-    if (j == 10)
-      dcmu = dl * f;
-    else
-      dc[j] = dl * f;
+  const T f = T(1) / (T(2) * c * m.rho);      // dc = d lambda / (2 c rho)
+  const Parts<T> p = cdm_parts(u, law);
+  const T vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+  const T q1 = T(1) + vn * vn;
+  dcmu = q1 * f;
+  if (p.guard) {
+    dc[9] = p.dac * m.xi0 * m.gr * q1 * f;
+    return c;
   }
+  const T im = p.im, sp = p.sp, I1p = p.I1p;
+  const T is = T(1) / sp, is2 = is * is, is3 = is2 * is;
+  T ep[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ep[k] = u[k] * im;
+  // E / max|eps| and its derivatives D_j = v.(d eps/du_j n)
+  const T en0 = ep[0] * n[0] + ep[3] * n[1] + ep[5] * n[2];
+  const T en1 = ep[3] * n[0] + ep[1] * n[1] + ep[4] * n[2];
+  const T en2 = ep[5] * n[0] + ep[4] * n[1] + ep[2] * n[2];
+  const T ve = v[0] * en0 + v[1] * en1 + v[2] * en2;
+  const T D[6] = {v[0] * n[0], v[1] * n[1], v[2] * n[2], v[0] * n[1] + v[1] * n[0],
+                  v[1] * n[2] + v[2] * n[1], v[2] * n[0] + v[0] * n[2]};
+  const T agr = p.ac * m.gr;
+  const T sc = agr * im * f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T wj = j < 3 ? T(1) : T(2);
+    const T ej = j < 3 ? T(1) : T(0);
+    const T G = wj * ep[j] * is;                        // ds/du_j
+    const T Xi = ej * is - I1p * wj * ep[j] * is3;      // dxi/du_j times max|eps|
+    const T t = T(-0.5) * Xi * q1 - T(2) * vn * (D[j] * is - G * ve * is2) +
+                ej * ve * ve * is3 - T(3) * I1p * G * ve * ve * is3 * is +
+                T(2) * I1p * ve * D[j] * is3;
+    dc[j] = sc * t;
+  }
+  dc[9] = p.dac * f *
+          ((m.xi0 * m.gr - T(0.5) * m.gr * p.xi) * q1 - T(2) * m.gr * is * vn * ve +
+           m.gr * I1p * is3 * ve * ve);
   return c;
 }
 
@@ -201,20 +222,26 @@ __device__ inline void llf_vjp_minus(const T* um, const T* up, const T n[3], con
   T ub[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) ub[k] = T(0.5) * (um[k] + up[k]);
-  T d1[10], d2[10], m1, m2;
+  T d1[10], m1;
   const T c1 = llf_speed_grad(ub, n, mm, law, d1, m1);
-  const T c2 = llf_speed_grad(ub, n, mp, law, d2, m2);
-  // tie rule: each side takes one half
-  const T a1 = c1 > c2 ? T(1) : (c1 < c2 ? T(0) : T(0.5));
-  const T a2 = T(1) - a1;
-  const T C = c1 > c2 ? c1 : c2;
+  T C = c1, a1 = T(0.5);
+  if (!same_material(mm, mp)) {
+    T d2[10], m2;
+    const T c2 = llf_speed_grad(ub, n, mp, law, d2, m2);
+    // tie rule: each side takes one half
+    a1 = c1 > c2 ? T(1) : (c1 < c2 ? T(0) : T(0.5));
+    const T a2 = T(1) - a1;
+    C = c1 > c2 ? c1 : c2;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) d1[k] = a1 * d1[k] + a2 * d2[k];
+  }
+  // equal materials: c1 = c2, a tie, and a1 d1 + a2 d2 = d1
   T jump = T(0);
 #pragma unroll
   for (int k = 0; k < 10; ++k) jump += w[k] * (um[k] - up[k]);
   // d/du-: C w/2 + (w . jump)/2 * dC/dubar * 1/2
 #pragma unroll
-  for (int k = 0; k < 10; ++k)
-    gu[k] += T(0.5) * C * w[k] + T(0.25) * jump * (a1 * d1[k] + a2 * d2[k]);
+  for (int k = 0; k < 10; ++k) gu[k] += T(0.5) * C * w[k] + T(0.25) * jump * d1[k];
   gmu += T(0.5) * jump * a1 * m1;
 }
 
@@ -260,25 +287,79 @@ __device__ inline void rate_vjp(const T* u, const MatP<T>& m, const Law<T>& law,
 }
 
 // tangent cotangent lt (6 x 7, the cell-average weight folded in): state
-// cotangent through the second derivatives of the stress (dual numbers)
+// cotangent through the second derivatives of the stress,
+//   gu_j = d/du_j sum_{k,c} lt[k][c] ds[k][c](u),
+// in closed form.  With G_q = ds/du_q = w_q u_q / s and Xi_q = dxi/du_q, every
+// singular term comes from the I1 sqrt(I2) part of the strain energy; in the
+// scale-free variables (eps / max|eps|) the strain derivatives carry one
+// factor 1/max|eps|.
 template <class T>
 __device__ inline void tangent_vjp(const T* u, const MatP<T>& m, const Law<T>& law,
                                    const T lt[6][7], T gu[10]) {
-  const Law<Dual<T>> ld = dual_law(law);
-  const MatP<Dual<T>> md = dual_mat(m, false);
-  Dual<T> ud[10];
-  Dual<T> ds[6][7];
-  for (int j = 0; j < 10; ++j) {
-    if (j >= 6 && j < 9) continue;              // velocities do not enter the tangent
-    dual_state(u, j, ud);
-    cdm_tangent(ud, md, ld, ds);
+  const Parts<T> p = cdm_parts(u, law);
+  T trT = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) trT += lt[k][k];
+  const T a6 = T(2) * m.xi0 * m.gr;
+  if (p.guard) {
+    // tangent: delta coef + e e lambda0, alpha column 2 xi0 gamma_r u_k (times dac)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) gu[j] += p.dac * a6 * lt[j][6];
+    gu[9] += p.dac * a6 * trT;
+    return;
+  }
+  const T im = p.im, sp = p.sp, I1p = p.I1p;
+  const T is = T(1) / sp, is2 = is * is, is3 = is2 * is;
+  T ep[6], G[6], Xp[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T w = k < 3 ? T(1) : T(2);
+    ep[k] = u[k] * im;
+    G[k] = w * ep[k] * is;
+    Xp[k] = (k < 3 ? is : T(0)) - I1p * w * ep[k] * is3;
+  }
+  // r_q = sum_{k<3} lt[k][q];  a_q = sum_k lt[k][q] ep_k;  (lt Xi)_k
+  T r[7], a[6], tX[6];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) r[q] = lt[0][q] + lt[1][q] + lt[2][q];
+  T rG = T(0), aG = T(0), ae = T(0), aX = T(0), t6e = T(0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
     T s = T(0);
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int c = 0; c < 7; ++c) s += lt[k][c] * ds[k][c].d;
-    gu[j] += s;
+    for (int k = 0; k < 6; ++k) s += lt[k][q] * ep[k];
+    a[q] = s;
+    rG += r[q] * G[q];
+    aG += s * G[q];
+    aX += s * Xp[q];
+    if (q < 3) ae += s;
+    t6e += lt[q][6] * ep[q];
   }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s += lt[k][q] * Xp[q];
+    tX[k] = s;
+  }
+  const T agr = p.ac * m.gr;
+  const T sc = agr * im;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const T wj = j < 3 ? T(1) : T(2);
+    const T ej = j < 3 ? T(1) : T(0);
+    // d/du_j of the 6 x 6 block: coef, e_k G_q, u_k Xi_q terms
+    const T A1 = -Xp[j] * trT;
+    const T A2 = -is * (r[j] * wj - G[j] * rG);
+    const T A3 = -tX[j];
+    const T A4 = (G[j] * ae + ej * aG) * is2 + I1p * wj * a[j] * is3 -
+                 T(3) * I1p * G[j] * aG * is3;
+    T g = sc * (A1 + A2 + A3 + A4);
+    // alpha column: dac (-e_k gamma_r s + (2 xi0 - xi) gamma_r u_k)
+    g += p.dac * (-m.gr * G[j] * r[6] - m.gr * Xp[j] * t6e + (a6 - m.gr * p.xi) * lt[j][6]);
+    gu[j] += g;
+  }
+  gu[9] += p.dac * ((a6 - m.gr * p.xi) * trT - m.gr * rG - m.gr * aX);
 }
 
 }  // namespace dgd

@@ -66,7 +66,8 @@ struct dgd_handle {
   // profiling: event pairs per kernel class
   // discrete adjoint: transposed reference data, adjoint state, checkpoints
   DevBuf VTpk, STpk, PTpk, KTpk;
-  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, save9, savea;
+  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, save9, savea;
+  void* uz_override = nullptr;   // time-point states of the step being replayed
   std::vector<DevBuf> ck9, cka;
   std::vector<double> ck_t;
   long long tape_steps = 0, tape_every = 0, tape_seis0 = 0;
@@ -80,7 +81,7 @@ struct dgd_handle {
                      &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
-                     &adjWa, &dlds, &seg9, &sega, &save9, &savea};
+                     &adjWa, &dlds, &seg9, &sega, &seguz, &save9, &savea};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
@@ -305,7 +306,7 @@ StepArgs<P> make_args(dgd_handle* h) {
   a.Ua = (const double*)h->Ua[c].p;
   a.W9 = (T*)h->U9[n].p;
   a.Wa = (double*)h->Ua[n].p;
-  a.Uz = (T*)h->Uz.p;
+  a.Uz = (T*)(h->uz_override ? h->uz_override : h->Uz.p);
   a.geo = (const double*)h->geo.p;
   a.fgeo = (const double*)h->fgeo.p;
   a.mat = (const double*)h->mat.p;
@@ -415,7 +416,7 @@ dgd_status alloc_adjoint(dgd_handle* h) {
 // material cotangents of this step to gmu, gcd
 template <int N, int P>
 dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, const void* lam_in,
-                             void* lam_out) {
+                             void* lam_out, void* uz) {
   using T = typename Prec<P>::T;
   using AF = typename Prec<P>::AF;
   if constexpr (P == PREC_BF16) {
@@ -424,6 +425,7 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     const long long per = (h->ne + 7) / 8;
     const dim3 grid((unsigned)(8 * per)), block(64);
     StepArgs<P> a = make_args<N, P>(h);
+    a.Uz = (T*)(uz ? uz : h->Uz.p);
     a.U9 = (const T*)U9;
     a.Ua = Ua;
     a.W9 = (T*)h->adjW9.p;
@@ -441,7 +443,9 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     A.beta = (const double*)h->betad.p;
     A.gmu = (double*)h->gmu.p;
     A.gcd = (double*)h->gcd.p;
-    timed(h, 4, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
+    // time-point states of this step: recomputed unless the replay kept them
+    if (!uz)
+      timed(h, 4, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
     timed(h, 5, [&] { hipLaunchKernelGGL((k_adj_face<N, P>), grid, block, 0, h->stream, A); });
     timed(h, 6, [&] { hipLaunchKernelGGL((k_adj_volume<N, P>), grid, block, 0, h->stream, A); });
     HIPCHK(h, hipGetLastError());
@@ -450,8 +454,9 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
 }
 
 template <int N, int P> struct AdjStepFn {
-  static dgd_status run(dgd_handle* h, const void* U9, const double* Ua, const void* li, void* lo) {
-    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo);
+  static dgd_status run(dgd_handle* h, const void* U9, const double* Ua, const void* li, void* lo,
+                        void* uz) {
+    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo, uz);
   }
 };
 
@@ -1132,7 +1137,7 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_o
     launch_lam_from_f64<float>(h, (const double*)h->scratch.p, h->lam[0].p);
   HIPCHK(h, hipGetLastError());
   if ((s = dispatch<AdjStepFn>(h, (const void*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
-                               (const void*)h->lam[0].p, h->lam[1].p)))
+                               (const void*)h->lam[0].p, h->lam[1].p, (void*)nullptr)))
     return s;
   if (h->prec == DGD_FP64)
     launch_lam_to_f64<double>(h, h->lam[1].p, (double*)h->scratch.p);
@@ -1201,6 +1206,14 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       (s = dalloc(h, h->seg9, (size_t)every * E * 9 * L * h->tsize)) ||
       (s = dalloc(h, h->sega, (size_t)every * E * L * sizeof(double))))
     return s;
+  // time-point states of every step of a segment, kept from the replay so
+  // that the adjoint need not recompute them (skipped if memory is short)
+  const size_t uzb = E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize;
+  bool keep_uz = dalloc(h, h->seguz, (size_t)every * uzb) == DGD_OK;
+  if (!keep_uz) {
+    (void)hipGetLastError();
+    h->err.clear();
+  }
   if (nrec > 0) {
     if ((s = dalloc(h, h->dlds, (size_t)nsteps * nrec * 3 * sizeof(double)))) return s;
     HIPCHK(h, hipMemcpyAsync(h->dlds.p, dl_dseis, (size_t)nsteps * nrec * 3 * sizeof(double),
@@ -1222,7 +1235,13 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       char* d9 = (char*)h->seg9.p + (size_t)(j - j0) * E * 9 * L * h->tsize;
       char* da = (char*)h->sega.p + (size_t)(j - j0) * E * L * sizeof(double);
       if ((s = copy_state(h, d9, da, h->U9[h->cur].p, h->Ua[h->cur].p))) break;
-      if (j + 1 < j1) s = dispatch<StepFn>(h, 1);
+      if (keep_uz) {
+        h->uz_override = (char*)h->seguz.p + (size_t)(j - j0) * uzb;
+        s = dispatch<StepFn>(h, 1);
+        h->uz_override = nullptr;
+      } else if (j + 1 < j1) {
+        s = dispatch<StepFn>(h, 1);
+      }
     }
     h->profiling = prof;
     for (long long j = j1 - 1; j >= j0 && s == DGD_OK; --j) {
@@ -1241,7 +1260,9 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       }
       const char* u9 = (const char*)h->seg9.p + (size_t)(j - j0) * E * 9 * L * h->tsize;
       const double* ua = (const double*)((const char*)h->sega.p + (size_t)(j - j0) * E * L * sizeof(double));
-      s = dispatch<AdjStepFn>(h, (const void*)u9, ua, (const void*)h->lam[lc].p, h->lam[1 - lc].p);
+      void* uz = keep_uz ? (void*)((char*)h->seguz.p + (size_t)(j - j0) * uzb) : nullptr;
+      s = dispatch<AdjStepFn>(h, (const void*)u9, ua, (const void*)h->lam[lc].p, h->lam[1 - lc].p,
+                              uz);
       lc = 1 - lc;
     }
   }
@@ -1268,6 +1289,7 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
   h->scratch.release();
   h->seg9.release();
   h->sega.release();
+  h->seguz.release();
   return DGD_OK;
 }
 

@@ -183,6 +183,12 @@ __device__ inline T llf_speed(const T* u, const T n[3], const MatP<T>& m, const 
   return lm > T(0) ? sqrt(lm) : T(0);
 }
 
+template <class T>
+__device__ inline bool same_material(const MatP<T>& a, const MatP<T>& b) {
+  return a.rho == b.rho && a.lam == b.lam && a.mu == b.mu && a.gr == b.gr && a.xi0 == b.xi0 &&
+         a.cd == b.cd;
+}
+
 // Local Lax-Friedrichs flux at one face point
 template <class T>
 __device__ inline void llf_flux(const T* um, const T* up, const T n[3], const MatP<T>& mm,
@@ -192,8 +198,13 @@ __device__ inline void llf_flux(const T* um, const T* up, const T n[3], const Ma
   normal_flux(up, n, mp, law, Fp);
 #pragma unroll
   for (int k = 0; k < 10; ++k) ub[k] = T(0.5) * (um[k] + up[k]);
-  T c1 = llf_speed(ub, n, mm, law), c2 = llf_speed(ub, n, mp, law);
-  T C = c1 > c2 ? c1 : c2;
+  // the speed at the mean state is the same for equal materials
+  const T c1 = llf_speed(ub, n, mm, law);
+  T C = c1;
+  if (!same_material(mm, mp)) {
+    const T c2 = llf_speed(ub, n, mp, law);
+    C = c1 > c2 ? c1 : c2;
+  }
 #pragma unroll
   for (int k = 0; k < 10; ++k) F[k] = T(0.5) * (Fm[k] + Fp[k]) + T(0.5) * C * (um[k] - up[k]);
 }
