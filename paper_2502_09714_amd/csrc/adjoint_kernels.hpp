@@ -44,8 +44,9 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
   constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
-  constexpr int TS = NST * 16 * 16;
-  static_assert(TS >= KPN * 16, "face buffer too small");
+  constexpr int R = Lds<T>::RS;
+  constexpr int TS = NST * 16 * R;
+  static_assert(TS >= KPN * R, "face buffer too small");
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
   __shared__ T sLm[TS];
@@ -73,14 +74,14 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
     for (int z = 0; z < Nt; ++z) {
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16, C,
-                             lane);
+      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64,
+                                 Uze + z * KPL * 16, C, lane);
       store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
     }
     {
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Le, C, lane);
+      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Le, C, lane);
       store_C<P, NST>(C, sLm, Ns, T(1), lane);
     }
     if (kind == 0) {
@@ -88,14 +89,14 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
       for (int z = 0; z < Nt; ++z) {
         Acc C[NST];
         zero_C<P, NST>(C);
-        wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                               Uzn + z * KPL * 16, C, lane);
+        wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                                   Uzn + z * KPL * 16, C, lane);
         store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
       }
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                             A.lam + (size_t)nb * KPL * 16, C, lane);
+      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                                 A.lam + (size_t)nb * KPL * 16, C, lane);
       store_C<P, NST>(C, sLp, Ns, T(1), lane);
     }
     __syncthreads();
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
     const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
     for (int idx = lane; idx < Ns * Nt; idx += 64) {
       const int z = idx / Ns, i = idx - z * Ns;
-      T* um = sTm + z * TS + i * 16;
+      T* um = sTm + z * TS + i * R;
       T uM[10], wv[10], gu[10];
       T gm = T(0);
       const T g = a.gamma[z];
@@ -122,13 +123,13 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
         T uP[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
-          uP[k] = sTp[z * TS + i * 16 + k];
-          wv[k] = g * (-se * sLm[i * 16 + k] + sn * sLp[i * 16 + k]);
+          uP[k] = sTp[z * TS + i * R + k];
+          wv[k] = g * (-se * sLm[i * R + k] + sn * sLp[i * R + k]);
         }
         llf_vjp_minus(uM, uP, n, m, mp, law, wv, gu, gm);
       } else {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) wv[k] = g * (-se * sLm[i * 16 + k]);
+        for (int k = 0; k < 10; ++k) wv[k] = g * (-se * sLm[i * R + k]);
         boundary_vjp(kind, uM, n, m, law, wv, gu, gm);
       }
       // the state cotangent takes the face weight through the lift below;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
   }
 #pragma unroll
   for (int z = 0; z < Nt; ++z)
-    store_C<P, MT>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
+    store_C<P, MT, 16>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
   const T gs = wave_sum(gmu);
   if (lane == 0) A.gmu[e] += (double)gs;
 }
@@ -160,10 +161,11 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   const StepArgs<P>& a = A.s;
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
+  constexpr int R = PredLDS<N, P>::R;
   __shared__ PredLDS<N, P> S;
-  __shared__ T sLam[KPL * 16];
-  __shared__ T sLU[Nt][KPL * 16];
-  __shared__ T sLD[N + 1][KPL * 16];
+  __shared__ T sLam[KPL * R];
+  __shared__ T sLU[Nt][KPL * R];
+  __shared__ T sLD[N + 1][KPL * R];
   __shared__ T sLA[300];
   __shared__ T sLds[48];
   T* const sX = S.B;
@@ -174,8 +176,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   predictor_stage<N, P>(a, e, S, m, lane);
-  for (int i = lane; i < KPL * 16; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
+  for (int i = lane; i < KPL * R; i += 64) {
+    const int l = i / R, k = i - l * R;
+    sLam[i] = k < 16 ? A.lam[((size_t)e * KPL + l) * 16 + k] : T(0);
+  }
   for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
+  for (int i = lane; i < Nt * KPL * R; i += 64) (&sLU[0][0])[i] = T(0);
   T Ji[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
       __syncthreads();
 #pragma unroll
-      for (int p = 0; p < 9; ++p) LG[c][ee * 9 + p] = sX[lane * 16 + p];
+      for (int p = 0; p < 9; ++p) LG[c][ee * 9 + p] = sX[lane * R + p];
       __syncthreads();
     }
     Acc C[4];
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
     store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
     __syncthreads();
-    Ls[c] = sX[lane * 16 + 9];
+    Ls[c] = sX[lane * R + 9];
     __syncthreads();
   }
 
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < L * 16; idx += 64) {
+    for (int idx = lane; idx < L * R; idx += 64) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * S.D[i][idx];
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       if (q < Q) {
         T u[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
         // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
         T ls[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -264,7 +270,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 16; ++k) sX[lane * 16 + k] = k < 10 ? gu[k] : T(0);
+      for (int k = 0; k < 16; ++k) sX[lane * R + k] = k < 10 ? gu[k] : T(0);
       __syncthreads();
       wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cl, lane);
       __syncthreads();
@@ -272,12 +278,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     store_C<P, MT>(Cl, sLU[z], KPL, T(1), lane);
     __syncthreads();
     const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
-    for (int idx = lane; idx < KPL * 16; idx += 64) sLU[z][idx] += lz[idx];
+    for (int idx = lane; idx < KPL * 16; idx += 64) sLU[z][(idx >> 4) * R + (idx & 15)] += lz[idx];
     __syncthreads();
   }
 
   // Taylor series reversed: dJ/dD^i = sum_z (tau_z dt)^i / i! dJ/dU_z
-  for (int idx = lane; idx < KPL * 16; idx += 64) {
+  for (int idx = lane; idx < KPL * R; idx += 64) {
 #pragma unroll
     for (int i = 0; i <= N; ++i) sLD[i][idx] = T(0);
   }
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     const T h = a.tau[z] * (T)a.dt;
     for (int i = 0; i <= N; ++i) {
       if (i > 0) cz = cz * h / T(i);
-      for (int idx = lane; idx < KPL * 16; idx += 64) sLD[i][idx] += cz * sLU[z][idx];
+      for (int idx = lane; idx < KPL * R; idx += 64) sLD[i][idx] += cz * sLU[z][idx];
     }
   }
   __syncthreads();
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       Acc C[MT];
       zero_C<P, MT>(C);
       wave_gemm<P, MT, KSL>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
-      store_C<P, MT>(C, S.B + ee * KPL * 16, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
+      store_C<P, MT>(C, S.B + ee * KPL * R, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
     }
     __syncthreads();
     // dJ/dD^{i-1} += sum_e dJ/dY_e A*_e
@@ -308,14 +314,14 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
 #pragma unroll
       for (int ee = 0; ee < 3; ++ee)
 #pragma unroll
-        for (int p = 0; p < 10; ++p) s += S.B[(ee * KPL + l) * 16 + p] * S.A[ee * 100 + p * 10 + q];
-      sLD[i - 1][l * 16 + q] += s;
+        for (int p = 0; p < 10; ++p) s += S.B[(ee * KPL + l) * R + p] * S.A[ee * 100 + p * 10 + q];
+      sLD[i - 1][l * R + q] += s;
     }
     // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]
     for (int idx = lane; idx < 300; idx += 64) {
       const int ee = idx / 100, p = (idx / 10) % 10, q = idx % 10;
       T s = T(0);
-      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * 16 + p] * S.D[i - 1][l * 16 + q];
+      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * R + p] * S.D[i - 1][l * R + q];
       sLA[idx] += s;
     }
     __syncthreads();
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
-    S.R[64 * c + lane] = sX[lane * 16 + 9];
+    S.R_[64 * c + lane] = sX[lane * R + 9];
     __syncthreads();
   }
   // dJ/dBbar through A*_e[6+i][q] = -(1/rho) sum_d Theta^-1_ed dsbar[sym(i,d)][col(q)]
@@ -370,18 +376,18 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     if (q < Q) {
       T u[10];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+      for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
       const T wgt = (T)A.wq[q] * a.inv_wsum;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
         for (int j = 0; j < 7; ++j) lt[k][j] = wgt * sLds[k * 7 + j];
       tangent_vjp(u, m, law, lt, gu);
-      rate_vjp(u, m, law, S.R[q], gu, gcd);
+      rate_vjp(u, m, law, S.R_[q], gu, gcd);
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) sX[lane * 16 + k] = k < 10 ? gu[k] : T(0);
+    for (int k = 0; k < 16; ++k) sX[lane * R + k] = k < 10 ? gu[k] : T(0);
     __syncthreads();
     wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cu, lane);
     __syncthreads();
@@ -390,7 +396,10 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   __syncthreads();
   // lambda^n = lambda^{n+1} (identity) + dJ/dD^0 + nodal path
   T* out = A.lamOut + (size_t)e * KPL * 16;
-  for (int idx = lane; idx < KPL * 16; idx += 64) out[idx] = sLam[idx] + sLD[0][idx] + S.W[idx];
+  for (int idx = lane; idx < KPL * 16; idx += 64) {
+    const int j = (idx >> 4) * R + (idx & 15);
+    out[idx] = sLam[j] + sLD[0][j] + S.W[j];
+  }
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
     A.gmu[e] += (double)gm;

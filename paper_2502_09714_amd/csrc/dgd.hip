@@ -43,7 +43,7 @@ struct dgd_handle {
   RefData ref;
   size_t tsize = 8;  // bytes of the working type
   // reference data on the device
-  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Wpk, Vd, wqd, Pwd, betad;
+  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Vd, wqd, Pwd, betad;
   int kpl = 0;  // padded mode count of the time-point state layout
   double inv_wsum = 6.0, phi0_mean = 0.0;
   // mesh and material
@@ -77,7 +77,7 @@ struct dgd_handle {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 
   ~dgd_handle() {
-    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Wpk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
+    DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
                      &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
@@ -203,28 +203,20 @@ dgd_status build_packed(dgd_handle* h) {
                      },
                      DM::MT, KSN));
     }
-  // damage-source projection and cell-average weights in the accurate precision
+  // damage-source projection in the accurate precision
   constexpr int PA = Accurate<P>::value;
   constexpr int KSQA = 64 / Prec<PA>::KS;
-  std::vector<typename HostAF<PA>::type> pp, wp;
-  for (int c = 0; c < DM::NCH; ++c) {
+  std::vector<typename HostAF<PA>::type> pp;
+  for (int c = 0; c < DM::NCH; ++c)
     append(pp, pack_A<PA>(
                    [&](int m, int kk) {
                      int q = 64 * c + kk;
                      return (m < L && q < Q) ? r.Pw[(size_t)m * Q + q] : 0.0;
                    },
                    DM::MT, KSQA));
-    append(wp, pack_A<PA>(
-                   [&](int m, int kk) {
-                     int q = 64 * c + kk;
-                     return q < Q ? r.wq[q] : 0.0;
-                   },
-                   1, KSQA));
-  }
   dgd_status st;
   if ((st = upload(h, h->Vpk, v)) || (st = upload(h, h->Kpk, k)) || (st = upload(h, h->Spk, s)) ||
-      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)) ||
-      (st = upload(h, h->Wpk, wp)))
+      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)))
     return st;
   if constexpr (P != PREC_BF16) {
     // transposed operators of the discrete adjoint
@@ -317,7 +309,7 @@ StepArgs<P> make_args(dgd_handle* h) {
   a.Fpk = (const AF*)h->Fpk.p;
   a.Lpk = (const AF*)h->Lpk.p;
   a.Ppk = (const typename Prec<Accurate<P>::value>::AF*)h->Ppk.p;
-  a.Wpk = (const typename Prec<Accurate<P>::value>::AF*)h->Wpk.p;
+  a.wq = (const double*)h->wqd.p;
   a.dt = h->dt;
   a.amax = (T)h->amax;
   a.smin = (T)1e-15;   // guard sqrt(I2) <= 1e-15, i.e. I2 <= 1e-30, in every precision

@@ -58,7 +58,7 @@ template <int P> struct StepArgs {
   const AF* Fpk;        // face traces [f][perm]
   const AF* Lpk;        // lift [f][perm]
   const typename Prec<Accurate<P>::value>::AF* Ppk;   // w_q phi_l(xi_q) per chunk
-  const typename Prec<Accurate<P>::value>::AF* Wpk;   // w_q in every row, per chunk
+  const double* wq;     // [Q] volume quadrature weights
   double dt;
   T amax, smin, inv_wsum;
   T tau[8], gamma[8];
@@ -93,17 +93,19 @@ __device__ inline T wave_sum(T v) {
 __device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
 __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
-// LDS working set of the predictor of one element (one wavefront)
+// LDS working set of the predictor of one element (one wavefront).  Matrices
+// with 16 columns (the 10 quantities, padded) use the row stride R.
 template <int N, int P> struct PredLDS {
   using T = typename Prec<P>::T;
   static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
   static constexpr int KPL = round_up(L, Prec<P>::KS);
-  static constexpr int BIG = 64 * 16 > 3 * KPL * 16 ? 64 * 16 : 3 * KPL * 16;
-  T D[N + 1][KPL * 16];   // D^0 = U^n, D^1..D^N time derivatives, [l][16] layout
-  T W[KPL * 16];          // time-point state / scratch
+  static constexpr int R = Lds<T>::RS;
+  static constexpr int BIG = 64 * R > 3 * KPL * R ? 64 * R : 3 * KPL * R;
+  T D[N + 1][KPL * R];    // D^0 = U^n, D^1..D^N time derivatives, [l][R] layout
+  T W[KPL * R];           // time-point state / scratch
   T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
   T A[300];               // A*_e (3 x 10 x 10)
-  T R[NCH * 64];          // nodal damage rate at t_n
+  T R_[NCH * 64];         // nodal damage rate at t_n
   T Acc[48];              // cell-averaged tangent (6 x 7)
   T J[9];                 // Theta^-1
 };
@@ -122,23 +124,25 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   constexpr int L = DM::L, Q = DM::Q, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQA = 64 / PA::KS;
+  constexpr int R = PredLDS<N, P>::R;
   T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
 
-  for (int i = lane; i < (N + 1) * KPL * 16; i += 64) (&S.D[0][0])[i] = T(0);
-  for (int i = lane; i < KPL * 16; i += 64) S.W[i] = T(0);
+  for (int i = lane; i < (N + 1) * KPL * R; i += 64) (&S.D[0][0])[i] = T(0);
+  for (int i = lane; i < KPL * R; i += 64) S.W[i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
     const int p = i / L, l = i - p * L;
-    S.D[0][l * 16 + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
+    S.D[0][l * R + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
   }
   if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
 
-  // cell average of the pointwise tangent (weighted sum on the matrix cores)
-  // and nodal damage rate at t_n
-  typename PA::Acc Cav[3];
-  zero_C<PA_, 3>(Cav);
+  // cell average of the pointwise tangent, sum_q w_q ds_q / sum_q w_q: the
+  // weighted tangents go to LDS 16 entries at a time; lane (c, g) sums column
+  // c over the rows 16g..16g+15, the four partial sums meet by lane shuffles.
+  // Nodal damage rate at t_n on the way.
+  T cav[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
@@ -152,36 +156,47 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     if (q < Q) {
       T u[10];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+      for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
       cdm_tangent(u, m, law, ds);
       r = cdm_rate(u, m, law);
+      const T wq = (T)a.wq[q];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) ds[k][j] *= wq;
     } else {
 #pragma unroll
       for (int k = 0; k < 6; ++k)
 #pragma unroll
         for (int j = 0; j < 7; ++j) ds[k][j] = T(0);
     }
-    S.R[q] = r;
+    S.R_[q] = r;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       __syncthreads();
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const int j = 16 * t + jj;
-        sX[lane * 16 + jj] = j < 42 ? ds[j / 7][j % 7] : T(0);
+        sX[lane * R + jj] = j < 42 ? ds[j / 7][j % 7] : T(0);
       }
       __syncthreads();
-      typename PA::Acc one[1] = {Cav[t]};
-      wave_gemm<PA_, 1, KSQA>(a.Wpk + (size_t)c * KSQA * 64, sX, one, lane);
-      Cav[t] = one[0];
+      const int col = lane & 15, g = lane >> 4;
+      T sum = T(0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sum += sX[(16 * g + ((i + g) & 15)) * R + col];
+      cav[t] += sum;
     }
     __syncthreads();
   }
-  // row 0 of every result tile sits in lanes 0..15, register 0
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    cav[t] += __shfl_xor(cav[t], 16, 64);
+    cav[t] += __shfl_xor(cav[t], 32, 64);
+  }
   if (lane < 16) {
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-      if (16 * t + lane < 42) S.Acc[16 * t + lane] = Cav[t][0] * a.inv_wsum;
+      if (16 * t + lane < 42) S.Acc[16 * t + lane] = cav[t] * a.inv_wsum;
   }
   __syncthreads();
 
@@ -207,26 +222,35 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     zero_C<PA_, MT>(Cs);
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
-      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R + 64 * c, Cs, lane);
-    store_C<PA_, MT>(Cs, S.W, L, T(1), lane);
+      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R_ + 64 * c, Cs, lane);
+    store_C<PA_, MT, R>(Cs, S.W, L, T(1), lane);
   }
+  // The right-hand-side buffer held nodal values before: clear it so that its
+  // padding rows and columns (read by the matrix cores against zero entries
+  // of K) are zero, not stale values.
+  for (int i = lane; i < 3 * KPL * R; i += 64) S.B[i] = T(0);
   __syncthreads();
 
-  // Cauchy-Kovalevskaya recursion.  The right-hand-side buffer held nodal
-  // values before: clear it so that its padding rows and columns (read by the
-  // matrix cores against zero A entries) are zero, not stale values.
-  for (int i = lane; i < 3 * KPL * 16; i += 64) S.B[i] = T(0);
-  __syncthreads();
+  // Cauchy-Kovalevskaya recursion.  Y_e = D^{i-1} A*_e^T on the vector ALUs:
+  // lane (e, p) keeps row p of A*_e in registers and walks half of the modes,
+  // so that the D rows it reads are broadcast to the lanes sharing a mode.
+  constexpr int LH = (L + 1) / 2;
+  const int pr = lane % 30, half = lane / 30;
+  const int pe = pr / 10, pp = pr % 10;
+  T Arow[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) Arow[q] = S.A[pe * 100 + pp * 10 + q];
 #pragma unroll
   for (int i = 1; i <= N; ++i) {
-    for (int idx = lane; idx < 3 * L * 10; idx += 64) {
-      const int ee = idx / (L * 10), r = idx - ee * L * 10, l = r / 10, p = r - l * 10;
-      const T* Ar = S.A + ee * 100 + p * 10;
-      const T* Dr = &S.D[i - 1][l * 16];
-      T s = T(0);
+    if (half < 2) {
+      const int l0 = half * LH, l1 = half ? L : LH;
+      for (int l = l0; l < l1; ++l) {
+        const T* Dr = &S.D[i - 1][l * R];
+        T s = T(0);
 #pragma unroll
-      for (int q = 0; q < 10; ++q) s += Dr[q] * Ar[q];
-      S.B[(ee * KPL + l) * 16 + p] = s;
+        for (int q = 0; q < 10; ++q) s += Dr[q] * Arow[q];
+        S.B[(pe * KPL + l) * R + pp] = s;
+      }
     }
     __syncthreads();
     Acc C[MT];
@@ -234,7 +258,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     wave_gemm<P, MT, 3 * KSL>(a.Kpk, S.B, C, lane);
     store_C<P, MT>(C, S.D[i], L, T(-1), lane);
     __syncthreads();
-    if (i == 1 && lane < L) S.D[1][lane * 16 + 9] += S.W[lane * 16 + 9];
+    if (i == 1 && lane < L) S.D[1][lane * R + 9] += S.W[lane * R + 9];
     __syncthreads();
   }
 }
@@ -250,6 +274,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  constexpr int R = PredLDS<N, P>::R;
   __shared__ PredLDS<N, P> S;
   T* const sX = S.B;
 
@@ -261,7 +286,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   predictor_stage<N, P>(a, e, S, m, lane);
   auto& sD = S.D;
   T* const sW = S.W;
-  T* const sR = S.R;
+  T* const sR = S.R_;
 
   // 4. time points and volume integrands
   T gacc[NCH][27];
@@ -283,15 +308,17 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < L * 16; idx += 64) {
+    for (int idx = lane; idx < L * R; idx += 64) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][idx];
       sW[idx] = v;
     }
     __syncthreads();
-    // time-point state in the [l][16] fragment layout (padding rows are zero)
-    for (int idx = lane; idx < KPL * 16; idx += 64) Uzo[z * KPL * 16 + idx] = sW[idx];
+    // time-point state to HBM in the [l][16] fragment layout (padding rows and
+    // columns are zero)
+    for (int idx = lane; idx < KPL * 16; idx += 64)
+      Uzo[z * KPL * 16 + idx] = sW[(idx >> 4) * R + (idx & 15)];
     const T g = a.gamma[z];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -304,10 +331,9 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
       if (q < Q) {
         T u[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) u[k] = sX[lane * 16 + k];
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
         T sig[6];
-        cdm_stress(u, m, law, sig);
-        sacc[c] += g * cdm_rate(u, m, law);
+        sacc[c] += g * cdm_stress_rate(u, m, law, sig);
         const T* v = u + 6;
 #pragma unroll
         for (int ee = 0; ee < 3; ++ee) {
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
 #pragma unroll
-      for (int p = 0; p < 16; ++p) sX[lane * 16 + p] = p < 9 ? gacc[c][ee * 9 + p] : T(0);
+      for (int p = 0; p < 16; ++p) sX[lane * R + p] = p < 9 ? gacc[c][ee * 9 + p] : T(0);
       __syncthreads();
       wave_gemm<P, MT, KSQ>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
       __syncthreads();
@@ -355,15 +381,15 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     for (int c = 0; c < NCH; ++c)
       wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Cs, lane);
     // column 9 of sW is zero (no damage flux): the source takes its place
-    store_C<PA_, MT>(Cs, sX, L, T(1), lane);
+    store_C<PA_, MT, R>(Cs, sX, L, T(1), lane);
   }
   __syncthreads();
   T* W9 = a.W9 + e * 9 * L;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    W9[idx] = sD[0][l * 16 + p] + sW[l * 16 + p];
+    W9[idx] = sD[0][l * R + p] + sW[l * R + p];
   }
-  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * 16 + 9]);
+  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * R + 9]);
 }
 
 template <int N, int P>
@@ -375,17 +401,18 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
   constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
-  constexpr int TS = NST * 16 * 16;
-  static_assert(Nt * TS >= MT * 16 * 16, "scratch too small");
+  constexpr int R = Lds<T>::RS;
+  constexpr int TS = NST * 16 * R;
+  static_assert(Nt * TS >= MT * 16 * R, "scratch too small");
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
-  __shared__ T sF[KPN * 16];
+  __shared__ T sF[KPN * R];
 
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
-  for (int i = lane; i < KPN * 16; i += 64) sF[i] = T(0);
+  for (int i = lane; i < KPN * R; i += 64) sF[i] = T(0);
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
   Acc Fc[MT];
@@ -399,8 +426,8 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
     for (int z = 0; z < Nt; ++z) {
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16, C,
-                             lane);
+      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64,
+                                 Uze + z * KPL * 16, C, lane);
       store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
     }
     if (kind == 0) {
@@ -409,8 +436,8 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
       for (int z = 0; z < Nt; ++z) {
         Acc C[NST];
         zero_C<P, NST>(C);
-        wave_gemm<P, NST, KSL>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                               Uzn + z * KPL * 16, C, lane);
+        wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                                   Uzn + z * KPL * 16, C, lane);
         store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
       }
     }
@@ -423,13 +450,13 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
     const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
     for (int idx = lane; idx < Ns * Nt; idx += 64) {
       const int z = idx / Ns, i = idx - z * Ns;
-      T* um = sTm + z * TS + i * 16;
+      T* um = sTm + z * TS + i * R;
       T uM[10], F[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) uM[k] = um[k];
       if (kind == 0) {
         T uP[10];
-        const T* up = sTp + z * TS + i * 16;
+        const T* up = sTp + z * TS + i * R;
 #pragma unroll
         for (int k = 0; k < 10; ++k) uP[k] = up[k];
         llf_flux(uM, uP, n, m, mp, law, F);
@@ -442,10 +469,11 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
     }
     __syncthreads();
     for (int idx = lane; idx < Ns * 16; idx += 64) {
+      const int i = idx >> 4, k = idx & 15;
       T s = T(0);
 #pragma unroll
-      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + idx];
-      sF[idx] = (idx & 15) < 10 ? s : T(0);
+      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + i * R + k];
+      sF[i * R + k] = k < 10 ? s : T(0);
     }
     __syncthreads();
     wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sF, Fc, lane);
@@ -457,12 +485,12 @@ __global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
   bool bad = false;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    const T v = W9[idx] - sTm[l * 16 + p];
+    const T v = W9[idx] - sTm[l * R + p];
     bad |= !isfinite(v);
     W9[idx] = v;
   }
   if (lane < L) {
-    const double v = a.Wa[e * L + lane] - (double)sTm[lane * 16 + 9];
+    const double v = a.Wa[e * L + lane] - (double)sTm[lane * R + 9];
     bad |= !isfinite(v);
     a.Wa[e * L + lane] = v;
   }

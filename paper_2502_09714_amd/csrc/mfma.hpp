@@ -43,9 +43,10 @@ template <> struct Prec<PREC_F64> {
   __device__ static inline Acc mma(AF a, AF b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  // B fragment from a [K][16] row-major LDS matrix
+  // B fragment from a [K][RS] row-major matrix (LDS or global)
+  template <int RS>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
-    return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
+    return B[(KS * s + (lane >> 4)) * RS + (lane & 15)];
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
     return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0;
@@ -61,8 +62,9 @@ template <> struct Prec<PREC_F32> {
   __device__ static inline Acc mma(AF a, AF b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  template <int RS>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
-    return B[(KS * s + (lane >> 4)) * 16 + (lane & 15)];
+    return B[(KS * s + (lane >> 4)) * RS + (lane & 15)];
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
     return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0f;
@@ -78,13 +80,14 @@ template <> struct Prec<PREC_BF16> {
   __device__ static inline Acc mma(AF a, AF b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
+  template <int RS>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
     int k0 = KS * s + 4 * (lane >> 4), n = lane & 15;
     AF r;
-    r[0] = (short)f32_to_bf16(B[(k0 + 0) * 16 + n]);
-    r[1] = (short)f32_to_bf16(B[(k0 + 1) * 16 + n]);
-    r[2] = (short)f32_to_bf16(B[(k0 + 2) * 16 + n]);
-    r[3] = (short)f32_to_bf16(B[(k0 + 3) * 16 + n]);
+    r[0] = (short)f32_to_bf16(B[(k0 + 0) * RS + n]);
+    r[1] = (short)f32_to_bf16(B[(k0 + 1) * RS + n]);
+    r[2] = (short)f32_to_bf16(B[(k0 + 2) * RS + n]);
+    r[3] = (short)f32_to_bf16(B[(k0 + 3) * RS + n]);
     return r;
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
@@ -99,21 +102,29 @@ template <> struct Prec<PREC_BF16> {
 
 __host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Row stride of per-element [rows][16-column] matrices kept in LDS.  A stride
+// of 16 puts the rows read one per lane (pointwise stages) on 4 of the 64
+// banks; 20 floats (80 B) / 18 doubles (144 B) keep 16-byte row alignment and
+// spread one row per lane, the C-fragment stores and the B-fragment loads over
+// all banks.
+template <class T> struct Lds { static constexpr int RS = sizeof(T) == 8 ? 18 : 20; };
+
 // The cell average of the tangent and the damage-source projections keep FP32
 // matrix-core inputs in the BF16 form (they feed the FP64 damage update).
 template <int P> struct Accurate { static constexpr int value = P == PREC_BF16 ? PREC_F32 : P; };
 
-// C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane].
+// C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane], B a
+// [K][RS] row-major matrix (RS = 16 for the global time-point states).
 // KSTEPS is a compile-time constant so that the loop unrolls and the A-fragment
 // loads are issued ahead of the matrix-core instructions that consume them.
-template <int P, int MT, int KSTEPS, int KSTRIDE = KSTEPS>
+template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS, int KSTRIDE = KSTEPS>
 __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
                                  const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT],
                                  int lane) {
   using PR = Prec<P>;
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    typename PR::AF b = PR::loadB(B, s, lane);
+    typename PR::AF b = PR::template loadB<RS>(B, s, lane);
 #pragma unroll
     for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
   }
@@ -133,8 +144,8 @@ __device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ A
   }
 }
 
-// Store C tiles to a [rows][16] LDS matrix, rows >= rmax dropped, times scale.
-template <int P, int MT>
+// Store C tiles to a [rows][RS] matrix, rows >= rmax dropped, times scale.
+template <int P, int MT, int RS = Lds<typename Prec<P>::T>::RS>
 __device__ inline void store_C(const typename Prec<P>::Acc (&C)[MT], typename Prec<P>::T* dst,
                                int rmax, typename Prec<P>::T scale, int lane) {
 #pragma unroll
@@ -142,7 +153,7 @@ __device__ inline void store_C(const typename Prec<P>::Acc (&C)[MT], typename Pr
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int r = 16 * t + Prec<P>::crow(lane, i);
-      if (r < rmax) dst[r * 16 + (lane & 15)] = scale * C[t][i];
+      if (r < rmax) dst[r * RS + (lane & 15)] = scale * C[t][i];
     }
 }
 

@@ -73,6 +73,18 @@ __device__ inline void cdm_stress(const T* u, const MatP<T>& m, const Law<T>& la
   for (int k = 0; k < 6; ++k) sig[k] = coef * u[k] + (k < 3 ? iso : T(0));
 }
 
+// stress and damage rate from one evaluation of the invariants
+template <class T>
+__device__ inline T cdm_stress_rate(const T* u, const MatP<T>& m, const Law<T>& law, T sig[6]) {
+  Parts<T> p = cdm_parts(u, law);
+  T iso = m.lam * p.I1 - p.ac * m.gr * p.s;
+  T coef = T(2) * (m.mu + p.ac * m.xi0 * m.gr) - p.ac * m.gr * p.xi;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig[k] = coef * u[k] + (k < 3 ? iso : T(0));
+  if (p.guard || !(p.xi > m.xi0)) return T(0);
+  return m.cd * m.gr * p.I2 * (p.xi - m.xi0);
+}
+
 template <class T>
 __device__ inline T cdm_rate(const T* u, const MatP<T>& m, const Law<T>& law) {
   Parts<T> p = cdm_parts(u, law);
