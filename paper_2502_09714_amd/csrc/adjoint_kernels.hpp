@@ -161,11 +161,11 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   const StepArgs<P>& a = A.s;
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
-  constexpr int R = PredLDS<N, P>::R;
+  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
+  static_assert(DS == 16, "adjoint states are exchanged with HBM row by row");
   __shared__ PredLDS<N, P> S;
-  __shared__ T sLam[KPL * R];
-  __shared__ T sLU[Nt][KPL * R];
-  __shared__ T sLD[N + 1][KPL * R];
+  __shared__ T sLam[KPL * DS];
+  __shared__ T sLD[N + 1][KPL * DS];
   __shared__ T sLA[300];
   __shared__ T sLds[48];
   T* const sX = S.B;
@@ -176,12 +176,9 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   predictor_stage<N, P>(a, e, S, m, lane);
-  for (int i = lane; i < KPL * R; i += 64) {
-    const int l = i / R, k = i - l * R;
-    sLam[i] = k < 16 ? A.lam[((size_t)e * KPL + l) * 16 + k] : T(0);
-  }
+  for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
   for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
-  for (int i = lane; i < Nt * KPL * R; i += 64) (&sLU[0][0])[i] = T(0);
+  for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&sLD[0][0])[i] = T(0);
   T Ji[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
@@ -198,7 +195,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C, lane);
+      wave_gemm<P, 4, KSL, DS>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C, lane);
       store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
       __syncthreads();
 #pragma unroll
@@ -207,21 +204,22 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     }
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
+    wave_gemm<P, 4, KSL, DS>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
     store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
     __syncthreads();
     Ls[c] = sX[lane * R + 9];
     __syncthreads();
   }
 
-  // volume and source cotangents at every time point -> dJ/dU_z
+  // volume and source cotangents at every time point -> dJ/dU_z, and the
+  // Taylor series reversed on the way: dJ/dD^i += (tau_z dt)^i / i! dJ/dU_z
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
     cz[0] = T(1);
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < L * R; idx += 64) {
+    for (int idx = lane; idx < KPL * DS; idx += 64) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * S.D[i][idx];
@@ -235,7 +233,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     for (int c = 0; c < NCH; ++c) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.W, C, lane);
+      wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, S.W, C, lane);
       store_C<P, 4>(C, sX, 64, T(1), lane);
       __syncthreads();
       const int q = 64 * c + lane;
@@ -275,27 +273,17 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cl, lane);
       __syncthreads();
     }
-    store_C<P, MT>(Cl, sLU[z], KPL, T(1), lane);
+    // S.W (the time-point state) is free now: dJ/dU_z goes there
+    store_C<P, MT, DS>(Cl, S.W, KPL, T(1), lane);
     __syncthreads();
     const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
-    for (int idx = lane; idx < KPL * 16; idx += 64) sLU[z][(idx >> 4) * R + (idx & 15)] += lz[idx];
+    for (int idx = lane; idx < KPL * DS; idx += 64) {
+      const T v = S.W[idx] + lz[idx];
+#pragma unroll
+      for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
+    }
     __syncthreads();
   }
-
-  // Taylor series reversed: dJ/dD^i = sum_z (tau_z dt)^i / i! dJ/dU_z
-  for (int idx = lane; idx < KPL * R; idx += 64) {
-#pragma unroll
-    for (int i = 0; i <= N; ++i) sLD[i][idx] = T(0);
-  }
-  for (int z = 0; z < Nt; ++z) {
-    T cz = T(1);
-    const T h = a.tau[z] * (T)a.dt;
-    for (int i = 0; i <= N; ++i) {
-      if (i > 0) cz = cz * h / T(i);
-      for (int idx = lane; idx < KPL * R; idx += 64) sLD[i][idx] += cz * sLU[z][idx];
-    }
-  }
-  __syncthreads();
 
   // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source)
   for (int i = N; i >= 1; --i) {
@@ -303,7 +291,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[MT];
       zero_C<P, MT>(C);
-      wave_gemm<P, MT, KSL>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
+      wave_gemm<P, MT, KSL, DS>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
       store_C<P, MT>(C, S.B + ee * KPL * R, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
     }
     __syncthreads();
@@ -315,13 +303,13 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       for (int ee = 0; ee < 3; ++ee)
 #pragma unroll
         for (int p = 0; p < 10; ++p) s += S.B[(ee * KPL + l) * R + p] * S.A[ee * 100 + p * 10 + q];
-      sLD[i - 1][l * R + q] += s;
+      sLD[i - 1][l * DS + q] += s;
     }
     // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]
     for (int idx = lane; idx < 300; idx += 64) {
       const int ee = idx / 100, p = (idx / 10) % 10, q = idx % 10;
       T s = T(0);
-      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * R + p] * S.D[i - 1][l * R + q];
+      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * R + p] * S.D[i - 1][l * DS + q];
       sLA[idx] += s;
     }
     __syncthreads();
@@ -331,7 +319,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
+    wave_gemm<P, 4, KSL, DS>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     S.R_[64 * c + lane] = sX[lane * R + 9];
@@ -366,7 +354,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
+    wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     const int q = 64 * c + lane;
@@ -392,14 +380,11 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cu, lane);
     __syncthreads();
   }
-  store_C<P, MT>(Cu, S.W, KPL, T(1), lane);
+  store_C<P, MT, DS>(Cu, S.W, KPL, T(1), lane);
   __syncthreads();
   // lambda^n = lambda^{n+1} (identity) + dJ/dD^0 + nodal path
   T* out = A.lamOut + (size_t)e * KPL * 16;
-  for (int idx = lane; idx < KPL * 16; idx += 64) {
-    const int j = (idx >> 4) * R + (idx & 15);
-    out[idx] = sLam[j] + sLD[0][j] + S.W[j];
-  }
+  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLam[idx] + sLD[0][idx] + S.W[idx];
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
     A.gmu[e] += (double)gm;

@@ -94,15 +94,17 @@ __device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
 __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
 // LDS working set of the predictor of one element (one wavefront).  Matrices
-// with 16 columns (the 10 quantities, padded) use the row stride R.
+// with 16 columns (the 10 quantities, padded) use the row stride R where they
+// are read or written one row per lane, 16 elsewhere.
 template <int N, int P> struct PredLDS {
   using T = typename Prec<P>::T;
   static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
   static constexpr int KPL = round_up(L, Prec<P>::KS);
-  static constexpr int R = Lds<T>::RS;
+  static constexpr int R = Lds<T>::RS;   // rows read one per lane
+  static constexpr int DS = 16;          // D, W: read linearly and as matrix-core B operands
   static constexpr int BIG = 64 * R > 3 * KPL * R ? 64 * R : 3 * KPL * R;
-  T D[N + 1][KPL * R];    // D^0 = U^n, D^1..D^N time derivatives, [l][R] layout
-  T W[KPL * R];           // time-point state / scratch
+  T D[N + 1][KPL * DS];   // D^0 = U^n, D^1..D^N time derivatives, [l][16] layout
+  T W[KPL * DS];          // time-point state / scratch
   T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
   T A[300];               // A*_e (3 x 10 x 10)
   T R_[NCH * 64];         // nodal damage rate at t_n
@@ -124,16 +126,16 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   constexpr int L = DM::L, Q = DM::Q, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQA = 64 / PA::KS;
-  constexpr int R = PredLDS<N, P>::R;
+  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
   T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
 
-  for (int i = lane; i < (N + 1) * KPL * R; i += 64) (&S.D[0][0])[i] = T(0);
-  for (int i = lane; i < KPL * R; i += 64) S.W[i] = T(0);
+  for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&S.D[0][0])[i] = T(0);
+  for (int i = lane; i < KPL * DS; i += 64) S.W[i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
     const int p = i / L, l = i - p * L;
-    S.D[0][l * R + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
+    S.D[0][l * DS + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
   }
   if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
@@ -147,7 +149,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
+    wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     const int q = 64 * c + lane;
@@ -223,7 +225,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
       wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R_ + 64 * c, Cs, lane);
-    store_C<PA_, MT, R>(Cs, S.W, L, T(1), lane);
+    store_C<PA_, MT, DS>(Cs, S.W, L, T(1), lane);
   }
   // The right-hand-side buffer held nodal values before: clear it so that its
   // padding rows and columns (read by the matrix cores against zero entries
@@ -245,7 +247,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     if (half < 2) {
       const int l0 = half * LH, l1 = half ? L : LH;
       for (int l = l0; l < l1; ++l) {
-        const T* Dr = &S.D[i - 1][l * R];
+        const T* Dr = &S.D[i - 1][l * DS];
         T s = T(0);
 #pragma unroll
         for (int q = 0; q < 10; ++q) s += Dr[q] * Arow[q];
@@ -256,9 +258,9 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     Acc C[MT];
     zero_C<P, MT>(C);
     wave_gemm<P, MT, 3 * KSL>(a.Kpk, S.B, C, lane);
-    store_C<P, MT>(C, S.D[i], L, T(-1), lane);
+    store_C<P, MT, DS>(C, S.D[i], L, T(-1), lane);
     __syncthreads();
-    if (i == 1 && lane < L) S.D[1][lane * R + 9] += S.W[lane * R + 9];
+    if (i == 1 && lane < L) S.D[1][lane * DS + 9] += S.W[lane * DS + 9];
     __syncthreads();
   }
 }
@@ -274,7 +276,8 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
-  constexpr int R = PredLDS<N, P>::R;
+  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
+  static_assert(DS == 16, "time-point states are copied to HBM row by row");
   __shared__ PredLDS<N, P> S;
   T* const sX = S.B;
 
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < L * R; idx += 64) {
+    for (int idx = lane; idx < L * DS; idx += 64) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][idx];
@@ -317,14 +320,13 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     __syncthreads();
     // time-point state to HBM in the [l][16] fragment layout (padding rows and
     // columns are zero)
-    for (int idx = lane; idx < KPL * 16; idx += 64)
-      Uzo[z * KPL * 16 + idx] = sW[(idx >> 4) * R + (idx & 15)];
+    for (int idx = lane; idx < KPL * 16; idx += 64) Uzo[z * KPL * 16 + idx] = sW[idx];
     const T g = a.gamma[z];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL>(a.Vpk + (size_t)c * 4 * KSL * 64, sW, C, lane);
+      wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, sW, C, lane);
       store_C<P, 4>(C, sX, 64, T(1), lane);
       __syncthreads();
       const int q = 64 * c + lane;
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) sR[64 * c + lane] = sacc[c];
-  store_C<P, MT>(Vc, sW, L, (T)a.dt, lane);
+  store_C<P, MT, DS>(Vc, sW, L, (T)a.dt, lane);
   __syncthreads();
   {
     typename PA::Acc Cs[MT];
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   T* W9 = a.W9 + e * 9 * L;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    W9[idx] = sD[0][l * R + p] + sW[l * R + p];
+    W9[idx] = sD[0][l * DS + p] + sW[l * DS + p];
   }
   if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * R + 9]);
 }
