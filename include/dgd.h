@@ -159,13 +159,14 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
 /* Per-kernel timing with HIP events recorded on the solver's stream around
  * every launch while profiling is on.  dgd_get_kernel_times synchronises,
  * returns the summed milliseconds and launch counts of the kernel classes
- * {0: predictor + volume, 1: faces + update, 2: sources, 3: receivers,
+ * {0: predictor + volume, 1: face fluxes, 2: sources, 3: receivers,
  *  4: adjoint's predictor recomputation, 5: adjoint faces, 6: adjoint
- *  volume + predictor, 7: adjoint receivers}
+ *  volume + predictor, 7: adjoint receivers, 8: lift of the face fluxes +
+ *  update}
  * since the last call, and resets them. */
-#define DGD_NUM_KERNEL_CLASSES 8
+#define DGD_NUM_KERNEL_CLASSES 9
 dgd_status dgd_set_profiling(dgd_handle* h, int on);
-dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms /* 8 */, int64_t* launches /* 8 */);
+dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms /* 9 */, int64_t* launches /* 9 */);
 
 /* Intermediate results of the last dgd_step call for testing: the time-point
  * states U(t_n + tau_z dt) of its last step, [ne][Nt][10][L] FP64 host.

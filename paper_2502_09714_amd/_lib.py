@@ -55,7 +55,7 @@ _SIGS = {
     "dgd_backward": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
     "dgd_release_tape": (ctypes.c_int, [H]),
 }
-NUM_KERNEL_CLASSES = 8
+NUM_KERNEL_CLASSES = 9
 
 
 def lib():

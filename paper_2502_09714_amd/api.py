@@ -168,9 +168,9 @@ class Simulation:
         self._chk(self._L.dgd_set_profiling(self.h, int(bool(on))))
 
     def get_kernel_times(self):
-        """(ms[8], launches[8]) for predictor+volume, faces+update, sources,
-        receivers, and the adjoint's predictor recomputation, faces, volume,
-        receivers."""
+        """(ms[9], launches[9]) for predictor+volume, face fluxes, sources,
+        receivers, the adjoint's predictor recomputation, faces, volume,
+        receivers, and the lift + update."""
         ms = np.zeros(NUM_KERNEL_CLASSES)
         n = np.zeros(NUM_KERNEL_CLASSES, dtype=np.int64)
         self._chk(self._L.dgd_get_kernel_times(self.h, _dp(ms), n.ctypes.data_as(c_i64p)))

@@ -1,5 +1,5 @@
 // Discrete adjoint of one ADER-DG step (device), transposing every stage of
-// k_predict_volume / k_face_update:  given U^n and lambda^{n+1} = dJ/dU^{n+1}
+// k_predict_volume / k_face_flux / k_lift_update:  given U^n and lambda^{n+1} = dJ/dU^{n+1}
 // it returns lambda^n = dJ/dU^n and accumulates dJ/dmu0, dJ/dC_d per element.
 //
 //   k_predict_volume (forward, recomputed)  ->  time-point states U_z of all elements

@@ -51,6 +51,8 @@ struct dgd_handle {
   bool have_mesh = false, have_mat = false, have_params = false, have_state = false;
   std::vector<double> X0, Jm, Jinv, detJ;  // host copies for point location
   DevBuf geo, fgeo, conn, mat;
+  DevBuf faces, fmap, fflux;   // face list (first side, second side), element -> face, face fluxes
+  long long nfaces = 0;
   std::vector<double> rho_h;
   // state
   DevBuf U9[2], Ua[2], Uz, flag, scratch;
@@ -78,7 +80,7 @@ struct dgd_handle {
 
   ~dgd_handle() {
     DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
-                     &conn, &mat, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
+                     &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
                      &adjWa, &dlds, &seg9, &sega, &seguz, &save9, &savea};
@@ -330,7 +332,15 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
   for (long long it = 0; it < nsteps; ++it) {
     StepArgs<P> a = make_args<N, P>(h);
     timed(h, 0, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
-    timed(h, 1, [&] { hipLaunchKernelGGL((k_face_update<N, P>), grid, block, 0, h->stream, a); });
+    const long long fper = (h->nfaces + 7) / 8;
+    timed(h, 1, [&] {
+      hipLaunchKernelGGL((k_face_flux<N, P>), dim3((unsigned)(8 * fper)), block, 0, h->stream, a,
+                         (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
+    });
+    timed(h, 8, [&] {
+      hipLaunchKernelGGL((k_lift_update<N, P>), grid, block, 0, h->stream, a,
+                         (const int*)h->fmap.p, (const T*)h->fflux.p);
+    });
     if (h->nsrc > 0) {
       SrcArgs s;
       s.nsrc = h->nsrc;
@@ -567,6 +577,7 @@ dgd_status alloc_state(dgd_handle* h) {
     if ((s = dalloc(h, h->Ua[i], E * L * sizeof(double)))) return s;
   }
   if ((s = dalloc(h, h->Uz, E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize))) return s;
+  if ((s = dalloc(h, h->fflux, (size_t)h->nfaces * h->ref.Ns * 10 * h->tsize))) return s;
   if ((s = dalloc(h, h->flag, sizeof(int)))) return s;
   HIPCHK(h, hipMemsetAsync(h->flag.p, 0, sizeof(int), h->stream));
   return DGD_OK;
@@ -744,9 +755,39 @@ dgd_status dgd_set_mesh(dgd_handle* h, int64_t nv, const double* xyz, int64_t ne
     }
     i += 2;
   }
+  // face list: every interior face once (first side = the lower element*4+face),
+  // every boundary face once; faces follow their first element's order
+  std::vector<int> faces, fmap((size_t)ne * 4, -1);
+  faces.reserve((size_t)ne * 4);
+  long long nfaces = 0;
+  for (long long ef = 0; ef < ne * 4; ++ef) {
+    const int kind = conn_kind(conn[ef * 2 + 1]);
+    if (kind != 0) {
+      faces.push_back((int)ef);
+      faces.push_back(-1);
+      fmap[ef] = (int)(nfaces * 2);
+      ++nfaces;
+    } else {
+      const long long of = (long long)conn[ef * 2] * 4 + conn_nface(conn[ef * 2 + 1]);
+      if (of > ef) {
+        faces.push_back((int)ef);
+        faces.push_back((int)of);
+        fmap[ef] = (int)(nfaces * 2);
+        fmap[of] = (int)(nfaces * 2 + 1);
+        ++nfaces;
+      } else if (of == ef) {
+        return fail(h, DGD_EINVAL, "face matched with itself");
+      }
+    }
+  }
+  if (nfaces * 2 > (long long)INT32_MAX) return fail(h, DGD_EINVAL, "too many faces");
+  for (long long ef = 0; ef < ne * 4; ++ef)
+    if (fmap[ef] < 0) return fail(h, DGD_EINVAL, "face without a face record");
   dgd_status s;
-  if ((s = upload(h, h->geo, geo)) || (s = upload(h, h->fgeo, fgeo)) || (s = upload(h, h->conn, conn)))
+  if ((s = upload(h, h->geo, geo)) || (s = upload(h, h->fgeo, fgeo)) || (s = upload(h, h->conn, conn)) ||
+      (s = upload(h, h->faces, faces)) || (s = upload(h, h->fmap, fmap)))
     return s;
+  h->nfaces = nfaces;
   if ((s = alloc_state(h))) return s;
   h->have_mesh = true;
   h->have_mat = false;

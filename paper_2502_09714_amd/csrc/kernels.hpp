@@ -11,9 +11,10 @@
 //   volume term dt sum_z gamma_z sum_e Sw^e F^e(U_z) and damage source
 //   (Eqs. 3rd term, rhs term; the nodal projection followed by the stiffness
 //   equals quadrature with Sw = w_q dphi/dxi), partial update written out.
-// k_face_update  (Appendix A.2 Eq. 2nd term, A.3)
+// k_face_flux  (Appendix A.2 Eq. 2nd term, A.3), one wavefront per face
 //   traces of both sides at the shared face points for every time point,
-//   LLF (or boundary) flux, time/space quadrature, lift, final update.
+//   LLF (or boundary) flux, time quadrature -> [face][Ns][10] in HBM.
+// k_lift_update  lift of the four face fluxes of an element, final update.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -394,105 +395,142 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * R + 9]);
 }
 
+// One wavefront per face (interior faces once, boundary faces once): traces of
+// both sides at the shared face points for every time point, LLF (or
+// boundary) flux with the normal of the face's first element, time quadrature.
+// Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_face_update(StepArgs<P> a) {
+__global__ __launch_bounds__(64) void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces,
+                                                  typename Prec<P>::T* fflux) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
   using DM = Dims<N>;
-  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
+  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
   constexpr int R = Lds<T>::RS;
   constexpr int TS = NST * 16 * R;
-  static_assert(Nt * TS >= MT * 16 * R, "scratch too small");
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
-  __shared__ T sF[KPN * R];
+
+  const int lane = threadIdx.x;
+  const long long fid = elem_of_block(nfaces);
+  if (fid >= nfaces) return;
+  const int ef = faces[fid * 2], of = faces[fid * 2 + 1];
+  const long long e = ef >> 2;
+  const int f = ef & 3;
+  const int w = a.conn[ef * 2 + 1];
+  const int kind = conn_kind(w), sp = conn_perm(w);
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  for (int z = 0; z < Nt; ++z) {
+    Acc C[NST];
+    zero_C<P, NST>(C);
+    wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16,
+                               C, lane);
+    store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+  }
+  long long nb = -1;
+  if (kind == 0) {
+    nb = of >> 2;
+    const int nf = of & 3, sq = conn_nperm(w);
+    const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+    for (int z = 0; z < Nt; ++z) {
+      Acc C[NST];
+      zero_C<P, NST>(C);
+      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
+                                 Uzn + z * KPL * 16, C, lane);
+      store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
+    }
+  }
+  __syncthreads();
+  T n[3];
+  n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
+  n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
+  n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
+  const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + nb * 8) : m;
+  for (int idx = lane; idx < Ns * Nt; idx += 64) {
+    const int z = idx / Ns, i = idx - z * Ns;
+    T* um = sTm + z * TS + i * R;
+    T uM[10], F[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) uM[k] = um[k];
+    if (kind == 0) {
+      T uP[10];
+      const T* up = sTp + z * TS + i * R;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) uP[k] = up[k];
+      llf_flux(uM, uP, n, m, mp, law, F);
+    } else {
+      boundary_flux(kind, uM, n, m, law, F);
+    }
+    const T g = a.gamma[z];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) um[k] = g * F[k];
+  }
+  __syncthreads();
+  T* out = fflux + (size_t)fid * Ns * 10;
+  for (int idx = lane; idx < Ns * 10; idx += 64) {
+    const int i = idx / 10, k = idx - i * 10;
+    T s = T(0);
+#pragma unroll
+    for (int z = 0; z < Nt; ++z) s += sTm[z * TS + i * R + k];
+    out[idx] = s;
+  }
+}
+
+// Face term and final update (Appendix A.2, Eq. time-integrated): each element
+// lifts the time-integrated flux of its four faces (negated where it is the
+// face's second element: the flux is single valued), scaled by dt |S_f|/|J|,
+// and subtracts it from the partial update of k_predict_volume.
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fmap,
+                                                    const typename Prec<P>::T* fflux) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Ns = DM::Ns, MT = DM::MT;
+  constexpr int KS = PR::KS;
+  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
+  constexpr int R = Lds<T>::RS;
+  constexpr int FS = KPN * R > MT * 16 * R ? KPN * R : MT * 16 * R;
+  __shared__ T sF[FS];
 
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
-  const Law<T> law{a.amax, a.smin};
-  for (int i = lane; i < KPN * R; i += 64) sF[i] = T(0);
-  const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  for (int i = lane; i < FS; i += 64) sF[i] = T(0);
   Acc Fc[MT];
   zero_C<P, MT>(Fc);
-  __syncthreads();
-
   for (int f = 0; f < 4; ++f) {
-    const int nb = a.conn[(e * 4 + f) * 2];
-    const int w = a.conn[(e * 4 + f) * 2 + 1];
-    const int kind = conn_kind(w), sp = conn_perm(w);
-    for (int z = 0; z < Nt; ++z) {
-      Acc C[NST];
-      zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64,
-                                 Uze + z * KPL * 16, C, lane);
-      store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
-    }
-    if (kind == 0) {
-      const int nf = conn_nface(w), sq = conn_nperm(w);
-      const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
-      for (int z = 0; z < Nt; ++z) {
-        Acc C[NST];
-        zero_C<P, NST>(C);
-        wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                                   Uzn + z * KPL * 16, C, lane);
-        store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
-      }
-    }
+    const int fm = fmap[e * 4 + f];
+    const long long fid = fm >> 1;
+    const int sp = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
+    const T sc = (T)((fm & 1 ? -1.0 : 1.0) * a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
+    const T* fl = fflux + (size_t)fid * Ns * 10;
     __syncthreads();
-    T n[3];
-    n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
-    n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
-    n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
-    const T fsc = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
-    const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
-    for (int idx = lane; idx < Ns * Nt; idx += 64) {
-      const int z = idx / Ns, i = idx - z * Ns;
-      T* um = sTm + z * TS + i * R;
-      T uM[10], F[10];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) uM[k] = um[k];
-      if (kind == 0) {
-        T uP[10];
-        const T* up = sTp + z * TS + i * R;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) uP[k] = up[k];
-        llf_flux(uM, uP, n, m, mp, law, F);
-      } else {
-        boundary_flux(kind, uM, n, m, law, F);
-      }
-      const T g = a.gamma[z] * fsc;
-#pragma unroll
-      for (int k = 0; k < 10; ++k) um[k] = g * F[k];
-    }
-    __syncthreads();
-    for (int idx = lane; idx < Ns * 16; idx += 64) {
-      const int i = idx >> 4, k = idx & 15;
-      T s = T(0);
-#pragma unroll
-      for (int z = 0; z < Nt; ++z) s += sTm[z * TS + i * R + k];
-      sF[i * R + k] = k < 10 ? s : T(0);
+    for (int idx = lane; idx < Ns * 10; idx += 64) {
+      const int i = idx / 10, k = idx - i * 10;
+      sF[i * R + k] = sc * fl[idx];
     }
     __syncthreads();
     wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sF, Fc, lane);
-    __syncthreads();
   }
-  store_C<P, MT>(Fc, sTm, L, T(1), lane);
+  __syncthreads();
+  store_C<P, MT>(Fc, sF, L, T(1), lane);
   __syncthreads();
   T* W9 = a.W9 + e * 9 * L;
   bool bad = false;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    const T v = W9[idx] - sTm[l * R + p];
+    const T v = W9[idx] - sF[l * R + p];
     bad |= !isfinite(v);
     W9[idx] = v;
   }
   if (lane < L) {
-    const double v = a.Wa[e * L + lane] - (double)sTm[lane * R + 9];
+    const double v = a.Wa[e * L + lane] - (double)sF[lane * R + 9];
     bad |= !isfinite(v);
     a.Wa[e * L + lane] = v;
   }
