@@ -30,6 +30,8 @@ template <int P> struct AdjArgs {
   const AF* KTpk;         // K^e^T per e          (L x L)
   const double* wq;       // [Q] volume weights
   const double* beta;     // [Ns] face weights
+  const T* Dkept;         // [E][N][KPL][16] predictor derivatives of this step (or null)
+  const T* Akept;         // [E][48] cell-averaged tangents of this step (or null)
   double* gmu;            // [E] dJ/dmu0 (accumulated)
   double* gcd;            // [E] dJ/dC_d (accumulated)
 };
@@ -175,7 +177,10 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  predictor_stage<N, P>(a, e, S, m, lane);
+  if (A.Dkept)
+    predictor_restore<N, P>(a, e, S, m, A.Dkept, A.Akept, lane);
+  else
+    predictor_stage<N, P>(a, e, S, m, lane);
   for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
   for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
   for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&sLD[0][0])[i] = T(0);
@@ -285,7 +290,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     __syncthreads();
   }
 
-  // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source)
+  // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source).
+  // All three contractions on the matrix cores; dJ/dA*_e stays in registers.
+  for (int i = lane; i < 3 * KPL * R; i += 64) S.B[i] = T(0);   // padding rows of dJ/dY_e
+  Acc CA[3];
+  zero_C<P, 3>(CA);
+  __syncthreads();
   for (int i = N; i >= 1; --i) {
 #pragma unroll
     for (int ee = 0; ee < 3; ++ee) {
@@ -295,25 +305,50 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       store_C<P, MT>(C, S.B + ee * KPL * R, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
     }
     __syncthreads();
-    // dJ/dD^{i-1} += sum_e dJ/dY_e A*_e
-    for (int idx = lane; idx < L * 10; idx += 64) {
-      const int l = idx / 10, q = idx - l * 10;
-      T s = T(0);
+    // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]   (A = dJ/dY_e^T from LDS)
+#pragma unroll
+    for (int ee = 0; ee < 3; ++ee)
+#pragma unroll
+      for (int st = 0; st < KSL; ++st) {
+        const T av = S.B[(ee * KPL + KS * st + (lane >> 4)) * R + (lane & 15)];
+        CA[ee] = PR::mma(av, PR::template loadB<DS>(S.D[i - 1], st, lane), CA[ee]);
+      }
+    // dJ/dD^{i-1}[l][q] += sum_e sum_p dJ/dY_e[l][p] A*_e[p][q]   (K = p, 3 steps)
+    {
+      Acc CD[MT];
+      zero_C<P, MT>(CD);
+      const int col = lane & 15;
 #pragma unroll
       for (int ee = 0; ee < 3; ++ee)
 #pragma unroll
-        for (int p = 0; p < 10; ++p) s += S.B[(ee * KPL + l) * R + p] * S.A[ee * 100 + p * 10 + q];
-      sLD[i - 1][l * DS + q] += s;
-    }
-    // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]
-    for (int idx = lane; idx < 300; idx += 64) {
-      const int ee = idx / 100, p = (idx / 10) % 10, q = idx % 10;
-      T s = T(0);
-      for (int l = 0; l < L; ++l) s += S.B[(ee * KPL + l) * R + p] * S.D[i - 1][l * DS + q];
-      sLA[idx] += s;
+        for (int st = 0; st < 3; ++st) {
+          const int k = KS * st + (lane >> 4);
+          const T bv = (k < 10 && col < 10) ? S.A[ee * 100 + k * 10 + col] : T(0);
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const int row = 16 * t + col;
+            const T av = (row < L && k < 10) ? S.B[(ee * KPL + row) * R + k] : T(0);
+            CD[t] = PR::mma(av, bv, CD[t]);
+          }
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4) {
+          const int r = 16 * t + PR::crow(lane, i4);
+          if (r < L) sLD[i - 1][r * DS + col] += CD[t][i4];
+        }
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int ee = 0; ee < 3; ++ee)
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4) {
+      const int r = PR::crow(lane, i4), c = lane & 15;
+      if (r < 10 && c < 10) sLA[ee * 100 + r * 10 + c] = CA[ee][i4];
+    }
+  __syncthreads();
   // damage source at t_n: dJ/dr_q = (Pw^T dJ/dD^1)_q in column 9
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {

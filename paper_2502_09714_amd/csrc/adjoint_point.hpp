@@ -79,28 +79,44 @@ __device__ inline void dual_state(const T* u, int j, Dual<T>* ud) {
   for (int k = 0; k < 10; ++k) ud[k] = Dual<T>(u[k], k == j ? T(1) : T(0));
 }
 
-// stress cotangent ls (6) -> state and mu0 cotangents, through the exact tangent
+// stress cotangent ls (6) -> state and mu0 cotangents: ls^T d sigma/du in
+// closed form.  With sigma_k = coef u_k + e_k iso (e_k = 1 on the normal
+// entries), G_q = ds/du_q and Xi_q = dxi/du_q:
+//   sum_k ls_k dsigma_k/du_q = coef ls_q + e_q lambda0 tr(ls) - a gamma_r tr(ls) G_q
+//                              - a gamma_r (ls . eps) Xi_q,
+//   sum_k ls_k dsigma_k/dalpha = clamp' (-gamma_r s tr(ls) + (2 xi0 - xi) gamma_r (ls . eps)),
+//   sum_k ls_k dsigma_k/dmu0 = 2 (ls . eps).
 template <class T>
 __device__ inline void stress_vjp(const T* u, const MatP<T>& m, const Law<T>& law, const T ls[6],
                                   T gu[10], T& gmu) {
-  T ds[6][7];
-  cdm_tangent(u, m, law, ds);
+  const Parts<T> p = cdm_parts(u, law);
+  const T agr = p.ac * m.gr;
+  const T coef = T(2) * (m.mu + p.ac * m.xi0 * m.gr) - agr * p.xi;
+  const T trl = ls[0] + ls[1] + ls[2];
+  T lu = T(0);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    T s = T(0);
+  for (int k = 0; k < 6; ++k) lu += ls[k] * u[k];
+  const T a6 = T(2) * m.xi0 * m.gr;
+  if (p.guard) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s += ls[k] * ds[k][q];
-    gu[q] += s;
+    for (int q = 0; q < 6; ++q) gu[q] += coef * ls[q] + (q < 3 ? m.lam * trl : T(0));
+    gu[9] += p.dac * a6 * lu;
+  } else {
+    const T im = p.im, is = T(1) / p.sp, is3 = is * is * is;
+    T lep = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lep += ls[k] * u[k] * im;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const T w = q < 3 ? T(1) : T(2);
+      const T epq = u[q] * im;
+      const T G = w * epq * is;
+      const T Xp = (q < 3 ? is : T(0)) - p.I1p * w * epq * is3;
+      gu[q] += coef * ls[q] + (q < 3 ? m.lam * trl : T(0)) - agr * (trl * G + lep * Xp);
+    }
+    gu[9] += p.dac * (-m.gr * p.s * trl + (a6 - m.gr * p.xi) * lu);
   }
-  T sa = T(0);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sa += ls[k] * ds[k][6];
-  gu[9] += sa;
-  // d sigma_k / d mu0 = 2 eps_k
-  T sm = T(0);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sm += ls[k] * T(2) * u[k];
-  gmu += sm;
+  gmu += T(2) * lu;
 }
 
 // w^T d(F_n)/du for the normal flux F_n = n_d F^d(u)

@@ -68,8 +68,10 @@ struct dgd_handle {
   // profiling: event pairs per kernel class
   // discrete adjoint: transposed reference data, adjoint state, checkpoints
   DevBuf VTpk, STpk, PTpk, KTpk;
-  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, save9, savea;
+  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, segd, segacc, save9, savea;
   void* uz_override = nullptr;   // time-point states of the step being replayed
+  void* d_keep = nullptr;        // where that replay keeps D^1..D^N (or null)
+  void* acc_keep = nullptr;      // where it keeps the cell-averaged tangents (or null)
   std::vector<DevBuf> ck9, cka;
   std::vector<double> ck_t;
   long long tape_steps = 0, tape_every = 0, tape_seis0 = 0;
@@ -83,7 +85,7 @@ struct dgd_handle {
                      &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
-                     &adjWa, &dlds, &seg9, &sega, &seguz, &save9, &savea};
+                     &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
@@ -312,6 +314,8 @@ StepArgs<P> make_args(dgd_handle* h) {
   a.Lpk = (const AF*)h->Lpk.p;
   a.Ppk = (const typename Prec<Accurate<P>::value>::AF*)h->Ppk.p;
   a.wq = (const double*)h->wqd.p;
+  a.Dkeep = (T*)h->d_keep;
+  a.Akeep = (T*)h->acc_keep;
   a.dt = h->dt;
   a.amax = (T)h->amax;
   a.smin = (T)1e-15;   // guard sqrt(I2) <= 1e-15, i.e. I2 <= 1e-30, in every precision
@@ -418,7 +422,7 @@ dgd_status alloc_adjoint(dgd_handle* h) {
 // material cotangents of this step to gmu, gcd
 template <int N, int P>
 dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, const void* lam_in,
-                             void* lam_out, void* uz) {
+                             void* lam_out, void* uz, const void* dk, const void* ak) {
   using T = typename Prec<P>::T;
   using AF = typename Prec<P>::AF;
   if constexpr (P == PREC_BF16) {
@@ -443,6 +447,8 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     A.KTpk = (const AF*)h->KTpk.p;
     A.wq = (const double*)h->wqd.p;
     A.beta = (const double*)h->betad.p;
+    A.Dkept = (const T*)dk;
+    A.Akept = (const T*)ak;
     A.gmu = (double*)h->gmu.p;
     A.gcd = (double*)h->gcd.p;
     // time-point states of this step: recomputed unless the replay kept them
@@ -457,8 +463,8 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
 
 template <int N, int P> struct AdjStepFn {
   static dgd_status run(dgd_handle* h, const void* U9, const double* Ua, const void* li, void* lo,
-                        void* uz) {
-    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo, uz);
+                        void* uz, const void* dk, const void* ak) {
+    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo, uz, dk, ak);
   }
 };
 
@@ -1170,7 +1176,8 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_o
     launch_lam_from_f64<float>(h, (const double*)h->scratch.p, h->lam[0].p);
   HIPCHK(h, hipGetLastError());
   if ((s = dispatch<AdjStepFn>(h, (const void*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
-                               (const void*)h->lam[0].p, h->lam[1].p, (void*)nullptr)))
+                               (const void*)h->lam[0].p, h->lam[1].p, (void*)nullptr,
+                               (const void*)nullptr, (const void*)nullptr)))
     return s;
   if (h->prec == DGD_FP64)
     launch_lam_to_f64<double>(h, h->lam[1].p, (double*)h->scratch.p);
@@ -1247,6 +1254,17 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
     (void)hipGetLastError();
     h->err.clear();
   }
+  // and the predictor's derivatives and cell-averaged tangents, so that the
+  // adjoint need not repeat the prediction either
+  const size_t db = E * (size_t)h->N * h->kpl * 16 * h->tsize, ab = E * 48 * h->tsize;
+  bool keep_d = keep_uz && dalloc(h, h->segd, (size_t)every * db) == DGD_OK &&
+                dalloc(h, h->segacc, (size_t)every * ab) == DGD_OK;
+  if (!keep_d) {
+    (void)hipGetLastError();
+    h->err.clear();
+    h->segd.release();
+    h->segacc.release();
+  }
   if (nrec > 0) {
     if ((s = dalloc(h, h->dlds, (size_t)nsteps * nrec * 3 * sizeof(double)))) return s;
     HIPCHK(h, hipMemcpyAsync(h->dlds.p, dl_dseis, (size_t)nsteps * nrec * 3 * sizeof(double),
@@ -1270,8 +1288,12 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       if ((s = copy_state(h, d9, da, h->U9[h->cur].p, h->Ua[h->cur].p))) break;
       if (keep_uz) {
         h->uz_override = (char*)h->seguz.p + (size_t)(j - j0) * uzb;
+        if (keep_d) {
+          h->d_keep = (char*)h->segd.p + (size_t)(j - j0) * db;
+          h->acc_keep = (char*)h->segacc.p + (size_t)(j - j0) * ab;
+        }
         s = dispatch<StepFn>(h, 1);
-        h->uz_override = nullptr;
+        h->uz_override = h->d_keep = h->acc_keep = nullptr;
       } else if (j + 1 < j1) {
         s = dispatch<StepFn>(h, 1);
       }
@@ -1294,8 +1316,10 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       const char* u9 = (const char*)h->seg9.p + (size_t)(j - j0) * E * 9 * L * h->tsize;
       const double* ua = (const double*)((const char*)h->sega.p + (size_t)(j - j0) * E * L * sizeof(double));
       void* uz = keep_uz ? (void*)((char*)h->seguz.p + (size_t)(j - j0) * uzb) : nullptr;
+      const void* dk = keep_d ? (const void*)((char*)h->segd.p + (size_t)(j - j0) * db) : nullptr;
+      const void* ak = keep_d ? (const void*)((char*)h->segacc.p + (size_t)(j - j0) * ab) : nullptr;
       s = dispatch<AdjStepFn>(h, (const void*)u9, ua, (const void*)h->lam[lc].p, h->lam[1 - lc].p,
-                              uz);
+                              uz, dk, ak);
       lc = 1 - lc;
     }
   }
@@ -1323,6 +1347,8 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
   h->seg9.release();
   h->sega.release();
   h->seguz.release();
+  h->segd.release();
+  h->segacc.release();
   return DGD_OK;
 }
 

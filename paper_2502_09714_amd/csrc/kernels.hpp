@@ -60,6 +60,8 @@ template <int P> struct StepArgs {
   const AF* Lpk;        // lift [f][perm]
   const typename Prec<Accurate<P>::value>::AF* Ppk;   // w_q phi_l(xi_q) per chunk
   const double* wq;     // [Q] volume quadrature weights
+  T* Dkeep;             // [E][N][KPL][16] D^1..D^N kept for the adjoint (or null)
+  T* Akeep;             // [E][48] cell-averaged tangent kept for the adjoint (or null)
   double dt;
   T amax, smin, inv_wsum;
   T tau[8], gamma[8];
@@ -112,6 +114,28 @@ template <int N, int P> struct PredLDS {
   T Acc[48];              // cell-averaged tangent (6 x 7)
   T J[9];                 // Theta^-1
 };
+
+// A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each), from
+// Theta^-1 (S.J) and the cell-averaged tangent (S.Acc)
+template <int N, int P>
+__device__ inline void build_Astar(PredLDS<N, P>& S, const MatP<typename Prec<P>::T>& m, int lane) {
+  using T = typename Prec<P>::T;
+  for (int i = lane; i < 300; i += 64) {
+    const int ee = i / 100, p = (i / 10) % 10, q = i % 10;
+    T v = T(0);
+    if (p < 6 && q >= 6 && q < 9) {
+      const int mm = q - 6, ii = kVI[p], jj = kVJ[p];
+      v = T(-0.5) * ((ii == mm ? S.J[ee * 3 + jj] : T(0)) + (jj == mm ? S.J[ee * 3 + ii] : T(0)));
+    } else if (p >= 6 && p < 9 && (q < 6 || q == 9)) {
+      const int ii = p - 6, col = q < 6 ? q : 6;
+      T s = T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s += S.J[ee * 3 + d] * S.Acc[sym_idx(ii, d) * 7 + col];
+      v = -s / m.rho;
+    }
+    S.A[i] = v;
+  }
+}
 
 // Prediction (Appendix A.1): load U^n, cell-averaged tangent, A*_e, damage
 // source at t_n, Cauchy-Kovalevskaya recursion.  Leaves D^0..D^N in S.D.
@@ -203,22 +227,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   }
   __syncthreads();
 
-  // A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each)
-  for (int i = lane; i < 300; i += 64) {
-    const int ee = i / 100, p = (i / 10) % 10, q = i % 10;
-    T v = T(0);
-    if (p < 6 && q >= 6 && q < 9) {
-      const int mm = q - 6, ii = kVI[p], jj = kVJ[p];
-      v = T(-0.5) * ((ii == mm ? S.J[ee * 3 + jj] : T(0)) + (jj == mm ? S.J[ee * 3 + ii] : T(0)));
-    } else if (p >= 6 && p < 9 && (q < 6 || q == 9)) {
-      const int ii = p - 6, col = q < 6 ? q : 6;
-      T s = T(0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) s += S.J[ee * 3 + d] * S.Acc[sym_idx(ii, d) * 7 + col];
-      v = -s / m.rho;
-    }
-    S.A[i] = v;
-  }
+  build_Astar<N, P>(S, m, lane);
   // damage source at t_n projected on the modes (lands in column 9 of W)
   {
     typename PA::Acc Cs[MT];
@@ -266,6 +275,35 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   }
 }
 
+// The predictor's results kept by an earlier launch of k_predict_volume on the
+// same state (D^1..D^N and the cell-averaged tangent): load them instead of
+// recomputing them.  Leaves S as predictor_stage does, except S.R_ and S.W.
+template <int N, int P>
+__device__ inline void predictor_restore(const StepArgs<P>& a, long long e, PredLDS<N, P>& S,
+                                         const MatP<typename Prec<P>::T>& m,
+                                         const typename Prec<P>::T* Dk,
+                                         const typename Prec<P>::T* Ak, int lane) {
+  using T = typename Prec<P>::T;
+  constexpr int L = Dims<N>::L;
+  constexpr int KPL = round_up(L, Prec<P>::KS), DS = PredLDS<N, P>::DS;
+  for (int i = lane; i < KPL * DS; i += 64) {
+    S.D[0][i] = T(0);
+    S.W[i] = T(0);
+  }
+  const T* U9 = a.U9 + e * 9 * L;
+  const T* De = Dk + (size_t)e * N * KPL * 16;
+  for (int i = lane; i < N * KPL * 16; i += 64) (&S.D[1][0])[i] = De[i];
+  if (lane < 48) S.Acc[lane] = Ak[e * 48 + lane];
+  if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
+  __syncthreads();
+  for (int i = lane; i < 10 * L; i += 64) {
+    const int p = i / L, l = i - p * L;
+    S.D[0][l * DS + p] = p < 9 ? U9[i] : (T)a.Ua[e * L + l];
+  }
+  build_Astar<N, P>(S, m, lane);
+  __syncthreads();
+}
+
 template <int N, int P>
 __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   using PR = Prec<P>;
@@ -288,6 +326,11 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   predictor_stage<N, P>(a, e, S, m, lane);
+  if (a.Dkeep) {
+    T* De = a.Dkeep + (size_t)e * N * KPL * 16;
+    for (int i = lane; i < N * KPL * 16; i += 64) De[i] = (&S.D[1][0])[i];
+    if (lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
+  }
   auto& sD = S.D;
   T* const sW = S.W;
   T* const sR = S.R_;
