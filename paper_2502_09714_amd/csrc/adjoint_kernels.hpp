@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   if (A.Dkept)
     predictor_restore<N, P>(a, e, S, m, A.Dkept, A.Akept, lane);
   else
-    predictor_stage<N, P>(a, e, S, m, lane);
+    predictor_stage<N, P, N + 1, false>(a, e, S, m, lane, nullptr);
   for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
   for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
   for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&sLD[0][0])[i] = T(0);

@@ -99,14 +99,19 @@ __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 // LDS working set of the predictor of one element (one wavefront).  Matrices
 // with 16 columns (the 10 quantities, padded) use the row stride R where they
 // are read or written one row per lane, 16 elsewhere.
-template <int N, int P> struct PredLDS {
+// ND = N + 1 keeps every time derivative in LDS (the adjoint needs them all);
+// ND = 2 keeps two (the one being formed and its predecessor) and leaves a
+// copy of each in registers, DPL values per lane, for the Taylor sums.
+template <int N, int P, int ND = N + 1> struct PredLDS {
   using T = typename Prec<P>::T;
   static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
   static constexpr int KPL = round_up(L, Prec<P>::KS);
   static constexpr int R = Lds<T>::RS;   // rows read one per lane
   static constexpr int DS = 16;          // D, W: read linearly and as matrix-core B operands
+  static constexpr int DPL = KPL * DS / 64;
+  static_assert(KPL * DS % 64 == 0, "derivatives split evenly over the lanes");
   static constexpr int BIG = 64 * R > 3 * KPL * R ? 64 * R : 3 * KPL * R;
-  T D[N + 1][KPL * DS];   // D^0 = U^n, D^1..D^N time derivatives, [l][16] layout
+  T D[ND][KPL * DS];      // time derivatives D^i in buffer i % ND, [l][16] layout
   T W[KPL * DS];          // time-point state / scratch
   T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
   T A[300];               // A*_e (3 x 10 x 10)
@@ -117,8 +122,9 @@ template <int N, int P> struct PredLDS {
 
 // A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each), from
 // Theta^-1 (S.J) and the cell-averaged tangent (S.Acc)
-template <int N, int P>
-__device__ inline void build_Astar(PredLDS<N, P>& S, const MatP<typename Prec<P>::T>& m, int lane) {
+template <int N, int P, int ND>
+__device__ inline void build_Astar(PredLDS<N, P, ND>& S, const MatP<typename Prec<P>::T>& m,
+                                   int lane) {
   using T = typename Prec<P>::T;
   for (int i = lane; i < 300; i += 64) {
     const int ee = i / 100, p = (i / 10) % 10, q = i % 10;
@@ -138,10 +144,13 @@ __device__ inline void build_Astar(PredLDS<N, P>& S, const MatP<typename Prec<P>
 }
 
 // Prediction (Appendix A.1): load U^n, cell-averaged tangent, A*_e, damage
-// source at t_n, Cauchy-Kovalevskaya recursion.  Leaves D^0..D^N in S.D.
-template <int N, int P>
-__device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P>& S,
-                                       const MatP<typename Prec<P>::T>& m, int lane) {
+// source at t_n, Cauchy-Kovalevskaya recursion.  Leaves D^0..D^N in S.D
+// (REGS false, ND = N + 1; dreg unused and may be null), or in
+// dreg[i * DPL + j] = D^i[lane + 64 j] (REGS true, ND = 2).
+template <int N, int P, int ND, bool REGS>
+__device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P, ND>& S,
+                                       const MatP<typename Prec<P>::T>& m, int lane,
+                                       typename Prec<P>::T* dreg) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
@@ -151,11 +160,13 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   constexpr int L = DM::L, Q = DM::Q, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQA = 64 / PA::KS;
-  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
+  constexpr int R = PredLDS<N, P, ND>::R, DS = PredLDS<N, P, ND>::DS;
+  constexpr int DPL = PredLDS<N, P, ND>::DPL;
+  static_assert(REGS ? ND == 2 : ND == N + 1, "two buffers with register copies, or all");
   T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
 
-  for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&S.D[0][0])[i] = T(0);
+  for (int i = lane; i < ND * KPL * DS; i += 64) (&S.D[0][0])[i] = T(0);
   for (int i = lane; i < KPL * DS; i += 64) S.W[i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
@@ -164,6 +175,10 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   }
   if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
+  if constexpr (REGS) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) dreg[j] = S.D[0][lane + 64 * j];
+  }
 
   // cell average of the pointwise tangent, sum_q w_q ds_q / sum_q w_q: the
   // weighted tangents go to LDS 16 entries at a time; lane (c, g) sums column
@@ -185,7 +200,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
 #pragma unroll
       for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
       cdm_tangent(u, m, law, ds);
-      r = cdm_rate(u, m, law);
+      r = -cdm_rate(u, m, law);   // negated: it joins the CK contraction stored with -1
       const T wq = (T)a.wq[q];
 #pragma unroll
       for (int k = 0; k < 6; ++k)
@@ -228,15 +243,6 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   __syncthreads();
 
   build_Astar<N, P>(S, m, lane);
-  // damage source at t_n projected on the modes (lands in column 9 of W)
-  {
-    typename PA::Acc Cs[MT];
-    zero_C<PA_, MT>(Cs);
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R_ + 64 * c, Cs, lane);
-    store_C<PA_, MT, DS>(Cs, S.W, L, T(1), lane);
-  }
   // The right-hand-side buffer held nodal values before: clear it so that its
   // padding rows and columns (read by the matrix cores against zero entries
   // of K) are zero, not stale values.
@@ -257,7 +263,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     if (half < 2) {
       const int l0 = half * LH, l1 = half ? L : LH;
       for (int l = l0; l < l1; ++l) {
-        const T* Dr = &S.D[i - 1][l * DS];
+        const T* Dr = &S.D[(i - 1) % ND][l * DS];
         T s = T(0);
 #pragma unroll
         for (int q = 0; q < 10; ++q) s += Dr[q] * Arow[q];
@@ -268,10 +274,20 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     Acc C[MT];
     zero_C<P, MT>(C);
     wave_gemm<P, MT, 3 * KSL>(a.Kpk, S.B, C, lane);
-    store_C<P, MT, DS>(C, S.D[i], L, T(-1), lane);
+    // damage source at t_n, projected on the modes in the same accumulators
+    // (column 9; the accurate precision's inputs, FP32 accumulation in the
+    // BF16 form): D^1 = -(sum_e K^e Y_e) + P r
+    if (i == 1) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R_ + 64 * c, C, lane);
+    }
+    store_C<P, MT, DS>(C, S.D[i % ND], L, T(-1), lane);
     __syncthreads();
-    if (i == 1 && lane < L) S.D[1][lane * DS + 9] += S.W[lane * DS + 9];
-    __syncthreads();
+    if constexpr (REGS) {
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) dreg[i * DPL + j] = S.D[i % 2][lane + 64 * j];
+    }
   }
 }
 
@@ -304,6 +320,15 @@ __device__ inline void predictor_restore(const StepArgs<P>& a, long long e, Pred
   __syncthreads();
 }
 
+// LDS derivative buffers of the forward predictor: two plus registers for the
+// FP32 / BF16 forms up to degree 3 (the smaller LDS footprint lets more
+// wavefronts share a compute unit), all of them otherwise (the register copy
+// would not fit: FP64, or 45 registers per lane at degree 4).
+template <int N, int P> struct FwdRegs {
+  static constexpr bool value = !(P == PREC_F64 || N >= 4);
+  static constexpr int ND = value ? 2 : N + 1;
+};
+
 template <int N, int P>
 __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   using PR = Prec<P>;
@@ -315,23 +340,36 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
-  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
+  constexpr bool REGS = FwdRegs<N, P>::value;
+  constexpr int ND = FwdRegs<N, P>::ND;
+  using SL = PredLDS<N, P, ND>;
+  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
   static_assert(DS == 16, "time-point states are copied to HBM row by row");
-  __shared__ PredLDS<N, P> S;
+  __shared__ SL S;
   T* const sX = S.B;
+  T dreg[(N + 1) * DPL];
 
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  predictor_stage<N, P>(a, e, S, m, lane);
+  predictor_stage<N, P, ND, REGS>(a, e, S, m, lane, dreg);
+  // D^i[idx] for idx = lane + 64 j
+  auto Dv = [&](int i, int j) -> T {
+    if constexpr (REGS)
+      return dreg[i * DPL + j];
+    else
+      return S.D[i][lane + 64 * j];
+  };
   if (a.Dkeep) {
     T* De = a.Dkeep + (size_t)e * N * KPL * 16;
-    for (int i = lane; i < N * KPL * 16; i += 64) De[i] = (&S.D[1][0])[i];
+#pragma unroll
+    for (int i = 1; i <= N; ++i)
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) De[(i - 1) * KPL * 16 + lane + 64 * j] = Dv(i, j);
     if (lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
   }
-  auto& sD = S.D;
   T* const sW = S.W;
   T* const sR = S.R_;
 
@@ -355,11 +393,12 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < L * DS; idx += 64) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
       T v = T(0);
 #pragma unroll
-      for (int i = 0; i <= N; ++i) v += cz[i] * sD[i][idx];
-      sW[idx] = v;
+      for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
+      sW[lane + 64 * j] = v;
     }
     __syncthreads();
     // time-point state to HBM in the [l][16] fragment layout (padding rows and
@@ -416,26 +455,27 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
       __syncthreads();
     }
   }
+  // damage source integral in the same accumulators: column 9 of the volume
+  // contraction is zero (no damage flux), the source takes its place
 #pragma unroll
   for (int c = 0; c < NCH; ++c) sR[64 * c + lane] = sacc[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+    wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Vc, lane);
   store_C<P, MT, DS>(Vc, sW, L, (T)a.dt, lane);
   __syncthreads();
-  {
-    typename PA::Acc Cs[MT];
-    zero_C<PA_, MT>(Cs);
+  // U^n + volume for the nine wave quantities (column 9 keeps the FP64 damage path)
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
-      wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Cs, lane);
-    // column 9 of sW is zero (no damage flux): the source takes its place
-    store_C<PA_, MT, R>(Cs, sX, L, T(1), lane);
-  }
+  for (int j = 0; j < DPL; ++j)
+    if (((lane + 64 * j) & 15) < 9) sW[lane + 64 * j] += Dv(0, j);
   __syncthreads();
   T* W9 = a.W9 + e * 9 * L;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    W9[idx] = sD[0][l * DS + p] + sW[l * DS + p];
+    W9[idx] = sW[l * DS + p];
   }
-  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)((T)a.dt * sX[lane * R + 9]);
+  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sW[lane * DS + 9];
 }
 
 // One wavefront per face (interior faces once, boundary faces once): traces of

@@ -102,12 +102,12 @@ template <> struct Prec<PREC_BF16> {
 
 __host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// Row stride of per-element [rows][16-column] matrices kept in LDS.  A stride
-// of 16 puts the rows read one per lane (pointwise stages) on 4 of the 64
-// banks; 20 floats (80 B) / 18 doubles (144 B) keep 16-byte row alignment and
-// spread one row per lane, the C-fragment stores and the B-fragment loads over
-// all banks.
-template <class T> struct Lds { static constexpr int RS = sizeof(T) == 8 ? 18 : 20; };
+// Row stride of per-element [rows][16-column] matrices that are read or
+// written one row per lane.  A stride of 16 puts those rows on 4 of the 64
+// banks; 18 elements (72 B for floats, 8-byte aligned rows; 144 B for
+// doubles) spread them over all banks and cost at most two-way conflicts in
+// the matrix-core fragment loads and stores.
+template <class T> struct Lds { static constexpr int RS = 18; };
 
 // The cell average of the tangent and the damage-source projections keep FP32
 // matrix-core inputs in the BF16 form (they feed the FP64 damage update).
