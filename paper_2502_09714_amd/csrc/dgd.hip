@@ -400,6 +400,18 @@ template <int N, int P> struct StepFn {
   static dgd_status run(dgd_handle* h, long long n) { return step_impl<N, P>(h, n); }
 };
 
+// the predictor of the current state only (time-point states and, when the
+// handle asks for them, the kept derivatives); state and time unchanged
+template <int N, int P> struct PredictFn {
+  static dgd_status run(dgd_handle* h) {
+    const long long per = (h->ne + 7) / 8;
+    StepArgs<P> a = make_args<N, P>(h);
+    hipLaunchKernelGGL((k_predict_volume<N, P>), dim3((unsigned)(8 * per)), dim3(64), 0, h->stream, a);
+    HIPCHK(h, hipGetLastError());
+    return DGD_OK;
+  }
+};
+
 // ---------------------------------------------------------------- discrete adjoint
 size_t lam_elems(const dgd_handle* h) { return (size_t)h->ne * h->kpl * 16; }
 
@@ -1292,7 +1304,8 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
           h->d_keep = (char*)h->segd.p + (size_t)(j - j0) * db;
           h->acc_keep = (char*)h->segacc.p + (size_t)(j - j0) * ab;
         }
-        s = dispatch<StepFn>(h, 1);
+        // the segment's last state is not stepped further: its prediction suffices
+        s = (j + 1 < j1) ? dispatch<StepFn>(h, 1) : dispatch<PredictFn>(h);
         h->uz_override = h->d_keep = h->acc_keep = nullptr;
       } else if (j + 1 < j1) {
         s = dispatch<StepFn>(h, 1);
