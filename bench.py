@@ -129,20 +129,35 @@ def run_precision(w, prec, steps, warmup, want_state=True):
     return out
 
 
-def run_adjoint(w, prec, steps, every):
+def run_adjoint(w, prec, steps, every, observed=False):
     """Checkpointed forward run (seismograms recorded) and the backward sweep
-    for the misfit J = |seismograms|^2 / 2: wall time of each and the
-    per-kernel times of the backward sweep."""
+    for the misfit J = |v - v_obs|^2 / 2 (v_obs from the run with mu0 and C_d
+    perturbed per element, if observed, else v_obs = 0): wall time of each and
+    the per-kernel times of the backward sweep."""
+    import numpy as np
     import torch
     from paper_2502_09714_amd.api import from_workload
+    from workloads.configs import perturbed_material
     sim = from_workload(w, prec)
     if sim.nrec == 0:
         m = w.mesh
         cent = m["xyz"][m["tets"][[0, w.ne // 3, w.ne // 2, (2 * w.ne) // 3]]].mean(axis=1)
         sim.set_receivers(cent)
     sim.set_check_interval(1 << 40)
+    U0 = sim.get_state()
+    base = dict(sim.material)
+    obs = 0.0
+    if observed:
+        sim.set_material(**perturbed_material(base, seed=2))
+        sim.step(steps)
+        obs = sim.get_seismograms()
+        sim.set_material(**base)
+    sim.set_state(U0)
+    sim.clear_seismograms()
     sim.forward_checkpointed(2, 1)          # warm-up of both sweeps
     sim.backward(sim.get_seismograms())
+    sim.set_state(U0)
+    sim.set_time(0.0)
     sim.clear_seismograms()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -154,14 +169,14 @@ def run_adjoint(w, prec, steps, every):
     sim.set_profiling(True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    gmu, gcd = sim.backward(seis)
+    gmu, gcd = sim.backward(seis - obs)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ms, launches = sim.get_kernel_times()
     sim.set_profiling(False)
     sim.close()
-    import numpy as np
-    return {"forward_s": t1 - t0, "backward_s": t3 - t2,
+    return {"workload": f"{w.name}: {w.ne} tets, N={w.N}, {len(seis[0])} receivers",
+            "forward_s": t1 - t0, "backward_s": t3 - t2,
             "backward_over_forward": (t3 - t2) / (t1 - t0),
             "backward_kernel_ms_per_step": {k: float(ms[i]) / steps for i, k in enumerate(KERNELS)
                                             if launches[i] > 0},
@@ -212,6 +227,9 @@ def main():
     ap.add_argument("--adjoint-precisions", default="fp32,fp64",
                     help="precisions whose checkpointed adjoint is timed ('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
+    ap.add_argument("--adjoint-workload", default="c4",
+                    help="workload of the full-length adjoint timing ('' for none)")
+    ap.add_argument("--adjoint-workload-precisions", default="fp32")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -289,6 +307,14 @@ def main():
         a = run_adjoint(w, p, args.steps, args.checkpoint_every)
         print(f"adjoint {p}: {a}", file=sys.stderr, flush=True)
         line[f"adjoint_{p}"] = a
+    if args.adjoint_workload:
+        # the differentiation-form workload: 82,944 tets, N=3, point source,
+        # 16 receivers, 400 steps with checkpoints every 20, FP32
+        wa = make_workload(args.adjoint_workload)
+        for p in [q.strip() for q in args.adjoint_workload_precisions.split(",") if q.strip()]:
+            a = run_adjoint(wa, p, wa.nsteps, 20, observed=True)
+            print(f"adjoint {args.adjoint_workload} {p}: {a}", file=sys.stderr, flush=True)
+            line[f"adjoint_{args.adjoint_workload}_{p}"] = a
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -46,17 +46,22 @@ __device__ inline Parts<T> cdm_parts(const T* u, const Law<T>& law) {
 #pragma unroll
   for (int k = 1; k < 6; ++k) m = fmax(m, fabs(u[k]));
   p.I1 = u[0] + u[1] + u[2];
-  const T im = m > T(0) ? T(1) / m : T(0);
+  // 1 / max|eps| only where it is finite: for max|eps| <= smin/4 (which in
+  // FP32 includes denormal strains, whose reciprocal overflows) sqrt(I2) <=
+  // 3 max|eps| is inside the guard anyway
+  const T im = m > law.smin * T(0.25) ? T(1) / m : T(0);
   const T e0 = u[0] * im, e1 = u[1] * im, e2 = u[2] * im, e3 = u[3] * im, e4 = u[4] * im,
           e5 = u[5] * im;
   const T I2p = e0 * e0 + e1 * e1 + e2 * e2 + T(2) * (e3 * e3 + e4 * e4 + e5 * e5);
-  p.sp = sqrt(I2p);
-  p.I1p = e0 + e1 + e2;
-  const T s = m * p.sp;
+  const T sp = sqrt(I2p);
+  const T I1p = e0 + e1 + e2;
+  const T s = m * sp;
   p.guard = !(s > law.smin);
   p.s = p.guard ? T(0) : s;
   p.I2 = s * s;
-  p.xi = p.guard ? T(0) : p.I1p / p.sp;
+  p.sp = p.guard ? T(0) : sp;
+  p.I1p = p.guard ? T(0) : I1p;
+  p.xi = p.guard ? T(0) : I1p / sp;
   p.im = p.guard ? T(0) : im;
   T a = u[9];
   p.ac = a < T(0) ? T(0) : (a > law.amax ? law.amax : a);

@@ -20,7 +20,7 @@ Workload recipe (seeds: 0 initial condition and material, 1 source,
 * ``c3`` as c2 with 64^3 cubes, N=4 and a lognormal (sigma 10 %, Gaussian
   correlation 200 m) perturbation of mu0 and lambda0; 1000 steps.
 * ``c4`` [0,24 km]^3, 24^3 cubes, N=3, c2's layered medium scaled to the box,
-  a 2 Hz Ricker moment-rate point source with random double-couple
+  a 2 Hz Ricker moment-rate point source 3 km below the free surface with random double-couple
   orientation, 16 receivers near the top face; 400 steps.
 * ``c5`` [0,24 km]^3, 96^3 cubes, N=4, a 3 km basin whose vs rises linearly
   from 300 m/s at the surface to 2000 m/s, 64 subfault point sources on a
@@ -282,9 +282,11 @@ def make_workload(name, n=None, N=None, nsteps=None, seed=0, periodic=None):
     src_rng = np.random.default_rng(seed + 1)
     if name == "c4":
         o = mesh["xyz"].min(axis=0)
+        # 3 km below the free surface (under the soft layer), so that the 400
+        # steps (~2 s) record arrivals at the receivers near the surface
         xs = o + np.array([ell / 2 + 0.0113 * mesh["edge"],
                            ell / 2 + 0.0079 * mesh["edge"],
-                           ell / 2 - 0.0053 * mesh["edge"]])
+                           ell - 3000.0 - 0.0053 * mesh["edge"]])
         f0 = 2.0
         wl.sources = dict(xyz=xs[None, :], M6=1e15 * _double_couple(src_rng)[None, :],
                           t_onset=np.array([1.2 / f0]), stf_param=np.array([f0]),
