@@ -3,14 +3,16 @@
 // it returns lambda^n = dJ/dU^n and accumulates dJ/dmu0, dJ/dC_d per element.
 //
 //   k_predict_volume (forward, recomputed)  ->  time-point states U_z of all elements
-//   k_adj_face   face terms: traces of U_z and of lambda at the shared face points,
-//                cotangent of the single-valued flux from both neighbours' updates,
-//                flux VJP, transposed trace (lift) -> dJ/dU_z (face part)
-//   k_adj_volume predictor recomputed; volume / source VJP at every (z, q);
-//                transposed nodal evaluation; Taylor and CK recursion reversed;
+//   k_adj_face   one wavefront per face: traces of U_z and of lambda on both
+//                sides, cotangent of the single-valued flux from both sides'
+//                updates, flux VJP for both traces -> trace cotangents per face
+//   k_adj_volume one wavefront per element: predictor restored or recomputed;
+//                volume / source VJP at every (z, q); transposed nodal
+//                evaluation and transposed lift of the four faces' trace
+//                cotangents; Taylor and CK recursion reversed;
 //                cell-averaged-tangent VJP (second derivatives of the stress);
 //                identity path -> lambda^n
-// One wavefront per element; every element writes only its own outputs.
+// Every wavefront writes only its own outputs (no atomics).
 #pragma once
 #include "adjoint_point.hpp"
 #include "kernels.hpp"
@@ -23,7 +25,10 @@ template <int P> struct AdjArgs {
   StepArgs<P> s;          // forward data (U^n in s.U9 / s.Ua, time points in s.Uz)
   const T* lam;           // [E][KPL][16] lambda^{n+1}
   T* lamOut;              // [E][KPL][16] lambda^n
-  T* lzf;                 // [E][Nt][KPL][16] face part of dJ/dU_z
+  T* gtr;                 // [face][side][Nt][Ns][10] cotangents of the face traces
+  T* lzf;                 // [E][Nt][KPL][16] their transposed lift (face part of dJ/dU_z)
+  double* gmuf;           // [face][side] face part of dJ/dmu0
+  const int* fmap;        // [E][4] face * 2 + side
   const AF* VTpk;         // V^T per chunk        (L x 64)
   const AF* STpk;         // Sw^e^T per e, chunk  (64 x L)
   const AF* PTpk;         // Pw^T per chunk       (64 x L)
@@ -36,122 +41,167 @@ template <int P> struct AdjArgs {
   double* gcd;            // [E] dJ/dC_d (accumulated)
 };
 
+// One wavefront per face (the face list of k_face_flux): traces of U_z and of
+// lambda^{n+1} on both sides at the shared face points.  The face flux F* is
+// single valued: the first side's update uses -dt|S|/|J| F*, the second side's
+// +dt|S'|/|J'| F*, so its cotangent at a point is
+// w = gamma_z (-s Lambda- + s' Lambda+).  The flux VJP gives the cotangents of
+// both traces, written to gtr[face][side][z][Ns][10] (lifted by k_adj_volume),
+// and of both sides' mu0, summed over the face points with their weights into
+// gmuf[face][side].
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A) {
+__global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
   using DM = Dims<N>;
   const StepArgs<P>& a = A.s;
-  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT, NST = DM::NST;
+  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
   constexpr int R = Lds<T>::RS;
   constexpr int TS = NST * 16 * R;
-  static_assert(TS >= KPN * R, "face buffer too small");
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
   __shared__ T sLm[TS];
   __shared__ T sLp[TS];
 
   const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  const long long fid = elem_of_block(nfaces);
+  if (fid >= nfaces) return;
+  const int ef = faces[fid * 2], of = faces[fid * 2 + 1];
+  const long long e = ef >> 2;
+  const int f = ef & 3;
+  const int w = a.conn[ef * 2 + 1];
+  const int kind = conn_kind(w), sp = conn_perm(w);
   const Law<T> law{a.amax, a.smin};
-  for (int i = lane; i < Nt * TS; i += 64) sTm[i] = T(0);
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
   const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
-  const T* Le = A.lam + (size_t)e * KPL * 16;
-  Acc Cz[Nt][MT];
-#pragma unroll
-  for (int z = 0; z < Nt; ++z) zero_C<P, MT>(Cz[z]);
-  T gmu = T(0);
-
-  for (int f = 0; f < 4; ++f) {
-    const int nb = a.conn[(e * 4 + f) * 2];
-    const int w = a.conn[(e * 4 + f) * 2 + 1];
-    const int kind = conn_kind(w), sp = conn_perm(w);
-    const int nf = conn_nface(w), sq = conn_nperm(w);
-    __syncthreads();
+  for (int z = 0; z < Nt; ++z) {
+    Acc C[NST];
+    zero_C<P, NST>(C);
+    wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
+    store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+  }
+  {
+    Acc C[NST];
+    zero_C<P, NST>(C);
+    wave_gemm<P, NST, KSL, 16>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
+    store_C<P, NST>(C, sLm, Ns, T(1), lane);
+  }
+  long long nb = -1;
+  int nf = 0;
+  if (kind == 0) {
+    nb = of >> 2;
+    nf = of & 3;
+    const typename PR::AF* Fn = a.Fpk + (size_t)(nf * 6 + conn_nperm(w)) * NST * KSL * 64;
+    const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
     for (int z = 0; z < Nt; ++z) {
       Acc C[NST];
       zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64,
-                                 Uze + z * KPL * 16, C, lane);
-      store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+      wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, C, lane);
+      store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
     }
-    {
-      Acc C[NST];
-      zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Le, C, lane);
-      store_C<P, NST>(C, sLm, Ns, T(1), lane);
+    Acc C[NST];
+    zero_C<P, NST>(C);
+    wave_gemm<P, NST, KSL, 16>(Fn, A.lam + (size_t)nb * KPL * 16, C, lane);
+    store_C<P, NST>(C, sLp, Ns, T(1), lane);
+  }
+  __syncthreads();
+  T n[3];
+  n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
+  n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
+  n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
+  const T se = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
+  const T sn = kind == 0 ? (T)(a.fgeo[(nb * 4 + nf) * 4 + 3] * a.dt) : T(0);
+  const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + nb * 8) : m;
+  T gmum = T(0), gmup = T(0);
+  T* g0 = A.gtr + (size_t)fid * 2 * Nt * Ns * 10;
+  T* g1 = g0 + Nt * Ns * 10;
+  for (int idx = lane; idx < Ns * Nt; idx += 64) {
+    const int z = idx / Ns, i = idx - z * Ns;
+    T uM[10], wv[10], gm[10], gp[10];
+    const T g = a.gamma[z];
+    const T bi = (T)A.beta[i];
+    T cm = T(0), cp = T(0);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      uM[k] = sTm[z * TS + i * R + k];
+      gm[k] = T(0);
+      gp[k] = T(0);
     }
     if (kind == 0) {
-      const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
-      for (int z = 0; z < Nt; ++z) {
-        Acc C[NST];
-        zero_C<P, NST>(C);
-        wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                                   Uzn + z * KPL * 16, C, lane);
-        store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
-      }
-      Acc C[NST];
-      zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                                 A.lam + (size_t)nb * KPL * 16, C, lane);
-      store_C<P, NST>(C, sLp, Ns, T(1), lane);
-    }
-    __syncthreads();
-    T n[3];
-    n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
-    n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
-    n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
-    // update of e: -dt |S|/|J_e| Lift F*;  update of the neighbour: +dt |S|/|J_nb| Lift' F*
-    const T se = (T)(a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
-    const T sn = kind == 0 ? (T)(a.fgeo[((size_t)nb * 4 + nf) * 4 + 3] * a.dt) : T(0);
-    const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + (size_t)nb * 8) : m;
-    for (int idx = lane; idx < Ns * Nt; idx += 64) {
-      const int z = idx / Ns, i = idx - z * Ns;
-      T* um = sTm + z * TS + i * R;
-      T uM[10], wv[10], gu[10];
-      T gm = T(0);
-      const T g = a.gamma[z];
+      T uP[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) {
-        uM[k] = um[k];
-        gu[k] = T(0);
+        uP[k] = sTp[z * TS + i * R + k];
+        wv[k] = g * (-se * sLm[i * R + k] + sn * sLp[i * R + k]);
       }
-      if (kind == 0) {
-        T uP[10];
+      llf_vjp_both(uM, uP, n, m, mp, law, wv, gm, gp, cm, cp);
+    } else {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
-          uP[k] = sTp[z * TS + i * R + k];
-          wv[k] = g * (-se * sLm[i * R + k] + sn * sLp[i * R + k]);
-        }
-        llf_vjp_minus(uM, uP, n, m, mp, law, wv, gu, gm);
-      } else {
+      for (int k = 0; k < 10; ++k) wv[k] = g * (-se * sLm[i * R + k]);
+      boundary_vjp(kind, uM, n, m, law, wv, gm, cm);
+    }
+    // the state cotangents take the face weight through the lift; the
+    // material cotangents take it here
+    gmum += bi * cm;
+    gmup += bi * cp;
 #pragma unroll
-        for (int k = 0; k < 10; ++k) wv[k] = g * (-se * sLm[i * R + k]);
-        boundary_vjp(kind, uM, n, m, law, wv, gu, gm);
-      }
-      // the state cotangent takes the face weight through the lift below;
-      // the material cotangent takes it here
-      gmu += (T)A.beta[i] * gm;
+    for (int k = 0; k < 10; ++k) g0[(z * Ns + i) * 10 + k] = gm[k];
+    if (kind == 0) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) um[k] = k < 10 ? gu[k] : T(0);
+      for (int k = 0; k < 10; ++k) g1[(z * Ns + i) * 10 + k] = gp[k];
+    }
+  }
+  const T s0 = wave_sum(gmum), s1 = wave_sum(gmup);
+  if (lane == 0) {
+    A.gmuf[fid * 2] = (double)s0;
+    A.gmuf[fid * 2 + 1] = (double)s1;
+  }
+}
+
+// One wavefront per element: the transposed lift of its four faces' trace
+// cotangents (the second side's negation is already in them), per time point
+// -> lzf[e][z] in the [l][16] layout.
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_adj_lift(AdjArgs<P> A) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  const StepArgs<P>& a = A.s;
+  constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS);
+  constexpr int KPN = round_up(Ns, KS), KSN = KPN / KS;
+  constexpr int R = Lds<T>::RS;
+  constexpr int GB = KPN * R;                      // one time point's cotangents, [Ns][R]
+  __shared__ T sG[Nt * GB];
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  for (int i = lane; i < Nt * GB; i += 64) sG[i] = T(0);
+  Acc Cz[Nt][MT];
+#pragma unroll
+  for (int z = 0; z < Nt; ++z) zero_C<P, MT>(Cz[z]);
+  for (int f = 0; f < 4; ++f) {
+    const int fm = A.fmap[e * 4 + f];
+    const int sp = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
+    const T* g = A.gtr + ((size_t)(fm >> 1) * 2 + (fm & 1)) * Nt * Ns * 10;
+    __syncthreads();
+    for (int idx = lane; idx < Nt * Ns * 10; idx += 64) {
+      const int zi = idx / 10, k = idx - zi * 10, z = zi / Ns, i = zi - z * Ns;
+      sG[z * GB + i * R + k] = g[idx];
     }
     __syncthreads();
-    // transposed trace: the lift matrix carries the face weights beta_i
 #pragma unroll
     for (int z = 0; z < Nt; ++z)
-      wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sTm + z * TS, Cz[z],
-                            lane);
+      wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sG + z * GB, Cz[z], lane);
   }
 #pragma unroll
   for (int z = 0; z < Nt; ++z)
     store_C<P, MT, 16>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
-  const T gs = wave_sum(gmu);
-  if (lane == 0) A.gmu[e] += (double)gs;
 }
 
 template <int N, int P>
@@ -191,11 +241,17 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   T gmu = T(0), gcd = T(0);
   __syncthreads();
 
-  // dJ/dG^e at the volume points: dt Sw^e^T lambda;  dJ/dr: dt Pw^T lambda_alpha
-  T LG[NCH][27];
+  // dJ/dG^e at the volume points: dt Sw^e^T lambda, folded at once into the
+  // cotangents of the velocity (LV) and of the stress (LS) at each point, per
+  // unit time weight (the flux is linear in both);  dJ/dr: dt Pw^T lambda_alpha
+  T LV[NCH][3], LS[NCH][6];
   T Ls[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) LV[c][k] = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) LS[c][k] = T(0);
 #pragma unroll
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[4];
@@ -203,8 +259,21 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       wave_gemm<P, 4, KSL, DS>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C, lane);
       store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
       __syncthreads();
+      // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
+      const T* Jr = Ji + ee * 3;
 #pragma unroll
-      for (int p = 0; p < 9; ++p) LG[c][ee * 9 + p] = sX[lane * R + p];
+      for (int p = 0; p < 6; ++p) {
+        const int ii = kVI[p], jj = kVJ[p];
+        const T lg = sX[lane * R + p];
+        LV[c][ii] += T(-0.5) * Jr[jj] * lg;
+        LV[c][jj] += T(-0.5) * Jr[ii] * lg;
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        const T lg = sX[lane * R + 6 + ii] * (-ir);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) LS[c][sym_idx(ii, d)] += lg * Jr[d];
+      }
       __syncthreads();
     }
     Acc C[4];
@@ -249,25 +318,11 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
         T u[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
-        // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
-        T ls[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T ls[6];
 #pragma unroll
-        for (int ee = 0; ee < 3; ++ee) {
-          const T* Jr = Ji + ee * 3;
+        for (int k = 0; k < 6; ++k) ls[k] = g * LS[c][k];
 #pragma unroll
-          for (int p = 0; p < 6; ++p) {
-            const int ii = kVI[p], jj = kVJ[p];
-            const T lg = g * LG[c][ee * 9 + p];
-            gu[6 + ii] += T(-0.5) * Jr[jj] * lg;
-            gu[6 + jj] += T(-0.5) * Jr[ii] * lg;
-          }
-#pragma unroll
-          for (int ii = 0; ii < 3; ++ii) {
-            const T lg = g * LG[c][ee * 9 + 6 + ii] * (-ir);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) ls[sym_idx(ii, d)] += lg * Jr[d];
-          }
-        }
+        for (int k = 0; k < 3; ++k) gu[6 + k] += g * LV[c][k];
         stress_vjp(u, m, law, ls, gu, gmu);
         rate_vjp(u, m, law, g * Ls[c], gu, gcd);
       }
@@ -422,7 +477,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLam[idx] + sLD[0][idx] + S.W[idx];
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
-    A.gmu[e] += (double)gm;
+    double gf = 0.0;
+    for (int f = 0; f < 4; ++f) {
+      const int fm = A.fmap[e * 4 + f];
+      gf += A.gmuf[(size_t)(fm >> 1) * 2 + (fm & 1)];
+    }
+    A.gmu[e] += (double)gm + gf;
     A.gcd[e] += (double)gc;
   }
 }

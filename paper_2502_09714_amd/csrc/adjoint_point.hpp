@@ -261,6 +261,47 @@ __device__ inline void llf_vjp_minus(const T* um, const T* up, const T n[3], con
   gmu += T(0.5) * jump * a1 * m1;
 }
 
+// Both sides at once: cotangents of u- and u+ and of each side's mu0 for the
+// flux cotangent w (the flux taken with the normal n of the minus side).
+// d/du+ differs from d/du- only in the sign of the C w / 2 term.
+template <class T>
+__device__ inline void llf_vjp_both(const T* um, const T* up, const T n[3], const MatP<T>& mm,
+                                    const MatP<T>& mp, const Law<T>& law, const T w[10],
+                                    T gm[10], T gp[10], T& gmum, T& gmup) {
+  T wh[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) wh[k] = T(0.5) * w[k];
+  normal_flux_vjp(um, n, mm, law, wh, gm, gmum);
+  normal_flux_vjp(up, n, mp, law, wh, gp, gmup);
+  T ub[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) ub[k] = T(0.5) * (um[k] + up[k]);
+  T d1[10], m1, m2;
+  const T c1 = llf_speed_grad(ub, n, mm, law, d1, m1);
+  T C = c1, a1 = T(0.5);
+  m2 = m1;
+  if (!same_material(mm, mp)) {
+    T d2[10];
+    const T c2 = llf_speed_grad(ub, n, mp, law, d2, m2);
+    a1 = c1 > c2 ? T(1) : (c1 < c2 ? T(0) : T(0.5));
+    const T a2 = T(1) - a1;
+    C = c1 > c2 ? c1 : c2;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) d1[k] = a1 * d1[k] + a2 * d2[k];
+  }
+  T jump = T(0);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) jump += w[k] * (um[k] - up[k]);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    const T cw = T(0.5) * C * w[k], dj = T(0.25) * jump * d1[k];
+    gm[k] += cw + dj;
+    gp[k] += dj - cw;
+  }
+  gmum += T(0.5) * jump * a1 * m1;
+  gmup += T(0.5) * jump * (T(1) - a1) * m2;
+}
+
 // boundary flux cotangents by forward-mode dual numbers
 template <class T>
 __device__ inline void boundary_vjp(int kind, const T* u, const T n[3], const MatP<T>& m,

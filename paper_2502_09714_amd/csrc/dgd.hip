@@ -68,7 +68,7 @@ struct dgd_handle {
   // profiling: event pairs per kernel class
   // discrete adjoint: transposed reference data, adjoint state, checkpoints
   DevBuf VTpk, STpk, PTpk, KTpk;
-  DevBuf lam[2], lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, segd, segacc, save9, savea;
+  DevBuf lam[2], gtr, gmuf, lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, segd, segacc, save9, savea;
   void* uz_override = nullptr;   // time-point states of the step being replayed
   void* d_keep = nullptr;        // where that replay keeps D^1..D^N (or null)
   void* acc_keep = nullptr;      // where it keeps the cell-averaged tangents (or null)
@@ -84,7 +84,7 @@ struct dgd_handle {
     DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
                      &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
-                     &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &lzf, &gmu, &gcd, &adjW9,
+                     &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &gtr, &gmuf, &lzf, &gmu, &gcd, &adjW9,
                      &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
@@ -420,6 +420,8 @@ dgd_status alloc_adjoint(dgd_handle* h) {
   dgd_status s;
   if ((s = dalloc(h, h->lam[0], lam_elems(h) * h->tsize)) ||
       (s = dalloc(h, h->lam[1], lam_elems(h) * h->tsize)) ||
+      (s = dalloc(h, h->gtr, (size_t)h->nfaces * 2 * h->ref.Nt * h->ref.Ns * 10 * h->tsize)) ||
+      (s = dalloc(h, h->gmuf, (size_t)h->nfaces * 2 * sizeof(double))) ||
       (s = dalloc(h, h->lzf, lam_elems(h) * h->ref.Nt * h->tsize)) ||
       (s = dalloc(h, h->gmu, E * sizeof(double))) || (s = dalloc(h, h->gcd, E * sizeof(double))) ||
       (s = dalloc(h, h->adjW9, E * 9 * L * h->tsize)) ||
@@ -452,7 +454,10 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     A.s = a;
     A.lam = (const T*)lam_in;
     A.lamOut = (T*)lam_out;
+    A.gtr = (T*)h->gtr.p;
+    A.gmuf = (double*)h->gmuf.p;
     A.lzf = (T*)h->lzf.p;
+    A.fmap = (const int*)h->fmap.p;
     A.VTpk = (const AF*)h->VTpk.p;
     A.STpk = (const AF*)h->STpk.p;
     A.PTpk = (const AF*)h->PTpk.p;
@@ -466,7 +471,12 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     // time-point states of this step: recomputed unless the replay kept them
     if (!uz)
       timed(h, 4, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
-    timed(h, 5, [&] { hipLaunchKernelGGL((k_adj_face<N, P>), grid, block, 0, h->stream, A); });
+    const long long fper = (h->nfaces + 7) / 8;
+    timed(h, 5, [&] {
+      hipLaunchKernelGGL((k_adj_face<N, P>), dim3((unsigned)(8 * fper)), block, 0, h->stream, A,
+                         (const int*)h->faces.p, h->nfaces);
+      hipLaunchKernelGGL((k_adj_lift<N, P>), grid, block, 0, h->stream, A);
+    });
     timed(h, 6, [&] { hipLaunchKernelGGL((k_adj_volume<N, P>), grid, block, 0, h->stream, A); });
     HIPCHK(h, hipGetLastError());
     return DGD_OK;

@@ -373,37 +373,37 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   T* const sW = S.W;
   T* const sR = S.R_;
 
-  // 4. time points and volume integrands
-  T gacc[NCH][27];
-  T sacc[NCH];
+  // 4. time points and volume integrands.  The flux is linear in the velocity
+  // and in the stress: only their time integrals sum_z gamma_z v(t_z) and
+  // sum_z gamma_z sigma(t_z) at each volume point are needed (and that of the
+  // damage rate); the Jacobian is applied once, in step 5.
+  T vs[NCH][3], ss[NCH][6], sacc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     sacc[c] = T(0);
 #pragma unroll
-    for (int k = 0; k < 27; ++k) gacc[c][k] = T(0);
+    for (int k = 0; k < 3; ++k) vs[c][k] = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ss[c][k] = T(0);
   }
   T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
-  const T ir = T(1) / m.rho;
-  T Ji[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
     cz[0] = T(1);
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+    // time-point state to LDS and to HBM in the [l][16] fragment layout
+    // (padding rows and columns are zero)
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
       sW[lane + 64 * j] = v;
+      Uzo[z * KPL * 16 + lane + 64 * j] = v;
     }
     __syncthreads();
-    // time-point state to HBM in the [l][16] fragment layout (padding rows and
-    // columns are zero)
-    for (int idx = lane; idx < KPL * 16; idx += 64) Uzo[z * KPL * 16 + idx] = sW[idx];
     const T g = a.gamma[z];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -419,37 +419,46 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
         for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
         T sig[6];
         sacc[c] += g * cdm_stress_rate(u, m, law, sig);
-        const T* v = u + 6;
 #pragma unroll
-        for (int ee = 0; ee < 3; ++ee) {
-          const T* Jr = Ji + ee * 3;
+        for (int k = 0; k < 6; ++k) ss[c][k] += g * sig[k];
 #pragma unroll
-          for (int p = 0; p < 6; ++p) {
-            const int ii = kVI[p], jj = kVJ[p];
-            gacc[c][ee * 9 + p] += g * (T(-0.5) * (Jr[jj] * v[ii] + Jr[ii] * v[jj]));
-          }
-#pragma unroll
-          for (int ii = 0; ii < 3; ++ii) {
-            T s = T(0);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) s += Jr[d] * sig[sym_idx(ii, d)];
-            gacc[c][ee * 9 + 6 + ii] += g * (-ir * s);
-          }
-        }
+        for (int k = 0; k < 3; ++k) vs[c][k] += g * u[6 + k];
       }
       __syncthreads();
     }
   }
 
-  // 5. volume contraction Vol = sum_e Sw^e G^e and damage source integral
+  // 5. volume contraction Vol = sum_e Sw^e G^e and damage source integral, with
+  // G^e_(ij) = -(Theta^-1_ej v_i + Theta^-1_ei v_j)/2 and
+  // G^e_(v_i) = -(1/rho) sum_d Theta^-1_ed sigma_id of the time integrals
+  const T ir = T(1) / m.rho;
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
   Acc Vc[MT];
   zero_C<P, MT>(Vc);
 #pragma unroll
   for (int ee = 0; ee < 3; ++ee) {
+    const T* Jr = Ji + ee * 3;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
+      T G[16];
 #pragma unroll
-      for (int p = 0; p < 16; ++p) sX[lane * R + p] = p < 9 ? gacc[c][ee * 9 + p] : T(0);
+      for (int p = 0; p < 6; ++p) {
+        const int ii = kVI[p], jj = kVJ[p];
+        G[p] = T(-0.5) * (Jr[jj] * vs[c][ii] + Jr[ii] * vs[c][jj]);
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        T t = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t += Jr[d] * ss[c][sym_idx(ii, d)];
+        G[6 + ii] = -ir * t;
+      }
+#pragma unroll
+      for (int p = 9; p < 16; ++p) G[p] = T(0);
+#pragma unroll
+      for (int p = 0; p < 16; ++p) sX[lane * R + p] = G[p];
       __syncthreads();
       wave_gemm<P, MT, KSQ>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
       __syncthreads();
