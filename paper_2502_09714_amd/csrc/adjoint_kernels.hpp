@@ -323,8 +323,9 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
         for (int k = 0; k < 6; ++k) ls[k] = g * LS[c][k];
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[6 + k] += g * LV[c][k];
-        stress_vjp(u, m, law, ls, gu, gmu);
-        rate_vjp(u, m, law, g * Ls[c], gu, gcd);
+        const Parts<T> pp = cdm_parts(u, law);
+        stress_vjp_p(pp, u, m, ls, gu, gmu);
+        rate_vjp_p(pp, u, m, g * Ls[c], gu, gcd);
       }
       __syncthreads();
 #pragma unroll
@@ -460,8 +461,9 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       for (int k = 0; k < 6; ++k)
 #pragma unroll
         for (int j = 0; j < 7; ++j) lt[k][j] = wgt * sLds[k * 7 + j];
-      tangent_vjp(u, m, law, lt, gu);
-      rate_vjp(u, m, law, S.R_[q], gu, gcd);
+      const Parts<T> pp = cdm_parts(u, law);
+      tangent_vjp_p(pp, u, m, lt, gu);
+      rate_vjp_p(pp, u, m, S.R_[q], gu, gcd);
     }
     __syncthreads();
 #pragma unroll

@@ -87,9 +87,8 @@ __device__ inline void dual_state(const T* u, int j, Dual<T>* ud) {
 //   sum_k ls_k dsigma_k/dalpha = clamp' (-gamma_r s tr(ls) + (2 xi0 - xi) gamma_r (ls . eps)),
 //   sum_k ls_k dsigma_k/dmu0 = 2 (ls . eps).
 template <class T>
-__device__ inline void stress_vjp(const T* u, const MatP<T>& m, const Law<T>& law, const T ls[6],
-                                  T gu[10], T& gmu) {
-  const Parts<T> p = cdm_parts(u, law);
+__device__ inline void stress_vjp_p(const Parts<T>& p, const T* u, const MatP<T>& m,
+                                    const T ls[6], T gu[10], T& gmu) {
   const T agr = p.ac * m.gr;
   const T coef = T(2) * (m.mu + p.ac * m.xi0 * m.gr) - agr * p.xi;
   const T trl = ls[0] + ls[1] + ls[2];
@@ -117,6 +116,12 @@ __device__ inline void stress_vjp(const T* u, const MatP<T>& m, const Law<T>& la
     gu[9] += p.dac * (-m.gr * p.s * trl + (a6 - m.gr * p.xi) * lu);
   }
   gmu += T(2) * lu;
+}
+
+template <class T>
+__device__ inline void stress_vjp(const T* u, const MatP<T>& m, const Law<T>& law, const T ls[6],
+                                  T gu[10], T& gmu) {
+  stress_vjp_p(cdm_parts(u, law), u, m, ls, gu, gmu);
 }
 
 // w^T d(F_n)/du for the normal flux F_n = n_d F^d(u)
@@ -329,18 +334,24 @@ __device__ inline void boundary_vjp(int kind, const T* u, const T n[3], const Ma
 // damage rate r = C_d gamma_r I2 (xi - xi0): state and C_d cotangents for the
 // rate cotangent lr
 template <class T>
-__device__ inline void rate_vjp(const T* u, const MatP<T>& m, const Law<T>& law, T lr, T gu[10],
-                                T& gcd) {
-  Parts<T> p = cdm_parts(u, law);
+__device__ inline void rate_vjp_p(const Parts<T>& p, const T* u, const MatP<T>& m, T lr, T gu[10],
+                                  T& gcd) {
   if (p.guard || !(p.xi > m.xi0)) return;
-  // r = C_d gamma_r (I1 s - xi0 I2),  ds/du_q = w_q u_q / s
+  // r = C_d gamma_r (I1 s - xi0 I2),  ds/du_q = w_q u_q / s,  I1 / s = xi
   const T k = lr * m.cd * m.gr;
+  const T c = p.xi - T(2) * m.xi0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const T wq = q < 3 ? T(1) : T(2);
-    gu[q] += k * ((q < 3 ? p.s : T(0)) + p.I1 * wq * u[q] / p.s - T(2) * m.xi0 * wq * u[q]);
+    gu[q] += k * ((q < 3 ? p.s : T(0)) + c * wq * u[q]);
   }
   gcd += lr * m.gr * p.I2 * (p.xi - m.xi0);
+}
+
+template <class T>
+__device__ inline void rate_vjp(const T* u, const MatP<T>& m, const Law<T>& law, T lr, T gu[10],
+                                T& gcd) {
+  rate_vjp_p(cdm_parts(u, law), u, m, lr, gu, gcd);
 }
 
 // tangent cotangent lt (6 x 7, the cell-average weight folded in): state
@@ -351,9 +362,8 @@ __device__ inline void rate_vjp(const T* u, const MatP<T>& m, const Law<T>& law,
 // scale-free variables (eps / max|eps|) the strain derivatives carry one
 // factor 1/max|eps|.
 template <class T>
-__device__ inline void tangent_vjp(const T* u, const MatP<T>& m, const Law<T>& law,
-                                   const T lt[6][7], T gu[10]) {
-  const Parts<T> p = cdm_parts(u, law);
+__device__ inline void tangent_vjp_p(const Parts<T>& p, const T* u, const MatP<T>& m,
+                                     const T lt[6][7], T gu[10]) {
   T trT = T(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) trT += lt[k][k];
