@@ -15,6 +15,10 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # keep packed FP32 instructions out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root by the hardware reciprocal / root
+    # (about 1 ulp) instead of the correctly rounded expansion; the FP32
+    # path's tolerances are orders of magnitude above that
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
 ]
 
 

@@ -216,11 +216,13 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
   static_assert(DS == 16, "adjoint states are exchanged with HBM row by row");
   __shared__ PredLDS<N, P> S;
-  __shared__ T sLam[KPL * DS];
+  // sLD[i] = dJ/dD^i; sLD[0] starts as lambda^{n+1} (the identity path) and
+  // ends as lambda^n minus the nodal path of the tangent and source at t_n
   __shared__ T sLD[N + 1][KPL * DS];
-  __shared__ T sLA[300];
   __shared__ T sLds[48];
   T* const sX = S.B;
+  T* const sLam = sLD[0];
+  T* const sLA = S.B;   // dJ/dA*_e, between the CK reversal and the t_n pass
 
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
@@ -232,8 +234,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   else
     predictor_stage<N, P, N + 1, false>(a, e, S, m, lane, nullptr);
   for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
-  for (int i = lane; i < 300; i += 64) sLA[i] = T(0);
-  for (int i = lane; i < (N + 1) * KPL * DS; i += 64) (&sLD[0][0])[i] = T(0);
+  for (int i = lane; i < N * KPL * DS; i += 64) (&sLD[1][0])[i] = T(0);
   T Ji[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
@@ -397,14 +398,6 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int ee = 0; ee < 3; ++ee)
-#pragma unroll
-    for (int i4 = 0; i4 < 4; ++i4) {
-      const int r = PR::crow(lane, i4), c = lane & 15;
-      if (r < 10 && c < 10) sLA[ee * 100 + r * 10 + c] = CA[ee][i4];
-    }
-  __syncthreads();
   // damage source at t_n: dJ/dr_q = (Pw^T dJ/dD^1)_q in column 9
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -416,6 +409,15 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     S.R_[64 * c + lane] = sX[lane * R + 9];
     __syncthreads();
   }
+  // dJ/dA*_e from the accumulators (S.B is free again)
+#pragma unroll
+  for (int ee = 0; ee < 3; ++ee)
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4) {
+      const int r = PR::crow(lane, i4), c = lane & 15;
+      if (r < 10 && c < 10) sLA[ee * 100 + r * 10 + c] = CA[ee][i4];
+    }
+  __syncthreads();
   // dJ/dBbar through A*_e[6+i][q] = -(1/rho) sum_d Theta^-1_ed dsbar[sym(i,d)][col(q)]
   if (lane < 42) {
     const int k = lane / 7, c = lane % 7, q = c < 6 ? c : 9;
@@ -474,9 +476,9 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   }
   store_C<P, MT, DS>(Cu, S.W, KPL, T(1), lane);
   __syncthreads();
-  // lambda^n = lambda^{n+1} (identity) + dJ/dD^0 + nodal path
+  // lambda^n = (lambda^{n+1} + dJ/dD^0, held in sLD[0]) + nodal path
   T* out = A.lamOut + (size_t)e * KPL * 16;
-  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLam[idx] + sLD[0][idx] + S.W[idx];
+  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLD[0][idx] + S.W[idx];
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
     double gf = 0.0;
