@@ -96,13 +96,29 @@ __device__ inline T wave_sum(T v) {
 __device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
 __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
+// The time-point buffer W and A*_e: separate, or (AW) sharing storage, which
+// the forward kernel can afford because it copies A*_e to registers before
+// the first time-point state is formed.
+template <class T, int NW, bool AW> struct PredWA {
+  T W[NW];                // time-point state / scratch
+  T A[300];               // A*_e (3 x 10 x 10)
+};
+template <class T, int NW> struct PredWA<T, NW, true> {
+  union {
+    T W[NW];
+    T A[300];
+  };
+};
+
 // LDS working set of the predictor of one element (one wavefront).  Matrices
 // with 16 columns (the 10 quantities, padded) use the row stride R where they
 // are read or written one row per lane, 16 elsewhere.
 // ND = N + 1 keeps every time derivative in LDS (the adjoint needs them all);
-// ND = 2 keeps two (the one being formed and its predecessor) and leaves a
-// copy of each in registers, DPL values per lane, for the Taylor sums.
-template <int N, int P, int ND = N + 1> struct PredLDS {
+// ND = 1 keeps only the one being formed (it overwrites its predecessor once
+// the right-hand sides are built) and leaves a copy of each in registers, DPL
+// values per lane, for the Taylor sums.
+template <int N, int P, int ND = N + 1, bool AW = false>
+struct PredLDS : PredWA<typename Prec<P>::T, round_up(Dims<N>::L, Prec<P>::KS) * 16, AW> {
   using T = typename Prec<P>::T;
   static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
   static constexpr int KPL = round_up(L, Prec<P>::KS);
@@ -112,9 +128,7 @@ template <int N, int P, int ND = N + 1> struct PredLDS {
   static_assert(KPL * DS % 64 == 0, "derivatives split evenly over the lanes");
   static constexpr int BIG = 64 * R > 3 * KPL * R ? 64 * R : 3 * KPL * R;
   T D[ND][KPL * DS];      // time derivatives D^i in buffer i % ND, [l][16] layout
-  T W[KPL * DS];          // time-point state / scratch
   T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
-  T A[300];               // A*_e (3 x 10 x 10)
   T R_[NCH * 64];         // nodal damage rate at t_n
   T Acc[48];              // cell-averaged tangent (6 x 7)
   T J[9];                 // Theta^-1
@@ -122,8 +136,8 @@ template <int N, int P, int ND = N + 1> struct PredLDS {
 
 // A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each), from
 // Theta^-1 (S.J) and the cell-averaged tangent (S.Acc)
-template <int N, int P, int ND>
-__device__ inline void build_Astar(PredLDS<N, P, ND>& S, const MatP<typename Prec<P>::T>& m,
+template <int N, int P, int ND, bool AW>
+__device__ inline void build_Astar(PredLDS<N, P, ND, AW>& S, const MatP<typename Prec<P>::T>& m,
                                    int lane) {
   using T = typename Prec<P>::T;
   for (int i = lane; i < 300; i += 64) {
@@ -146,9 +160,10 @@ __device__ inline void build_Astar(PredLDS<N, P, ND>& S, const MatP<typename Pre
 // Prediction (Appendix A.1): load U^n, cell-averaged tangent, A*_e, damage
 // source at t_n, Cauchy-Kovalevskaya recursion.  Leaves D^0..D^N in S.D
 // (REGS false, ND = N + 1; dreg unused and may be null), or in
-// dreg[i * DPL + j] = D^i[lane + 64 j] (REGS true, ND = 2).
-template <int N, int P, int ND, bool REGS>
-__device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P, ND>& S,
+// dreg[i * DPL + j] = D^i[lane + 64 j] (REGS true, ND = 1).  With AW, S.A is
+// not kept past the recursion.
+template <int N, int P, int ND, bool REGS, bool AW = false>
+__device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P, ND, AW>& S,
                                        const MatP<typename Prec<P>::T>& m, int lane,
                                        typename Prec<P>::T* dreg) {
   using PR = Prec<P>;
@@ -160,14 +175,13 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   constexpr int L = DM::L, Q = DM::Q, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQA = 64 / PA::KS;
-  constexpr int R = PredLDS<N, P, ND>::R, DS = PredLDS<N, P, ND>::DS;
-  constexpr int DPL = PredLDS<N, P, ND>::DPL;
-  static_assert(REGS ? ND == 2 : ND == N + 1, "two buffers with register copies, or all");
+  using SL = PredLDS<N, P, ND, AW>;
+  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
+  static_assert(REGS ? ND == 1 : ND == N + 1, "one buffer with register copies, or all");
   T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
 
   for (int i = lane; i < ND * KPL * DS; i += 64) (&S.D[0][0])[i] = T(0);
-  for (int i = lane; i < KPL * DS; i += 64) S.W[i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   for (int i = lane; i < 10 * L; i += 64) {
     const int p = i / L, l = i - p * L;
@@ -286,7 +300,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
     __syncthreads();
     if constexpr (REGS) {
 #pragma unroll
-      for (int j = 0; j < DPL; ++j) dreg[i * DPL + j] = S.D[i % 2][lane + 64 * j];
+      for (int j = 0; j < DPL; ++j) dreg[i * DPL + j] = S.D[i % ND][lane + 64 * j];
     }
   }
 }
@@ -320,17 +334,21 @@ __device__ inline void predictor_restore(const StepArgs<P>& a, long long e, Pred
   __syncthreads();
 }
 
-// LDS derivative buffers of the forward predictor: two plus registers for the
-// FP32 / BF16 forms up to degree 3 (the smaller LDS footprint lets more
-// wavefronts share a compute unit), all of them otherwise (the register copy
-// would not fit: FP64, or 45 registers per lane at degree 4).
+// LDS derivative buffers of the forward predictor: one plus registers up to
+// degree 3 (the smaller LDS footprint lets more wavefronts share a compute
+// unit), all of them at degree 4 (the register copy would not fit: 45 values
+// per lane).
 template <int N, int P> struct FwdRegs {
-  static constexpr bool value = !(P == PREC_F64 || N >= 4);
-  static constexpr int ND = value ? 2 : N + 1;
+  static constexpr bool value = N <= 3;
+  static constexpr int ND = value ? 1 : N + 1;
 };
 
+// With one LDS derivative buffer the FP32 / BF16 forms fit 21 workgroups per
+// compute unit; asking for five wavefronts per SIMD keeps the registers within
+// that (96 per lane).  The FP64 form is held to ten workgroups by its LDS.
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FwdRegs<N, P>::value ? (P == PREC_F64 ? 2 : 5) : 1)))
+void k_predict_volume(StepArgs<P> a) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
@@ -342,7 +360,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
   constexpr bool REGS = FwdRegs<N, P>::value;
   constexpr int ND = FwdRegs<N, P>::ND;
-  using SL = PredLDS<N, P, ND>;
+  using SL = PredLDS<N, P, ND, true>;
   constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
   static_assert(DS == 16, "time-point states are copied to HBM row by row");
   __shared__ SL S;
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(64) void k_predict_volume(StepArgs<P> a) {
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  predictor_stage<N, P, ND, REGS>(a, e, S, m, lane, dreg);
+  predictor_stage<N, P, ND, REGS, true>(a, e, S, m, lane, dreg);
   // D^i[idx] for idx = lane + 64 j
   auto Dv = [&](int i, int j) -> T {
     if constexpr (REGS)
