@@ -510,15 +510,17 @@ void k_predict_volume(StepArgs<P> a) {
 // boundary) flux with the normal of the face's first element, time quadrature.
 // Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces,
-                                                  typename Prec<P>::T* fflux) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 4 ? 1 : (P == PREC_F64 ? 4 : 6))))
+void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
   using DM = Dims<N>;
   constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int R = Lds<T>::RS;
+  // traces keep only the 10 quantities: an odd row stride reads one row per
+  // lane without bank conflicts and halves the LDS of the 16-column layout
+  constexpr int R = 11;
   constexpr int TS = NST * 16 * R;
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
@@ -539,7 +541,7 @@ __global__ __launch_bounds__(64) void k_face_flux(StepArgs<P> a, const int* face
     zero_C<P, NST>(C);
     wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16,
                                C, lane);
-    store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+    store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
   }
   long long nb = -1;
   if (kind == 0) {
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(64) void k_face_flux(StepArgs<P> a, const int* face
       zero_C<P, NST>(C);
       wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
                                  Uzn + z * KPL * 16, C, lane);
-      store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
+      store_C<P, NST, R, 10>(C, sTp + z * TS, Ns, T(1), lane);
     }
   }
   __syncthreads();

@@ -144,16 +144,18 @@ __device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ A
   }
 }
 
-// Store C tiles to a [rows][RS] matrix, rows >= rmax dropped, times scale.
-template <int P, int MT, int RS = Lds<typename Prec<P>::T>::RS>
+// Store C tiles to a [rows][RS] matrix, rows >= rmax and columns >= CMAX
+// dropped, times scale.
+template <int P, int MT, int RS = Lds<typename Prec<P>::T>::RS, int CMAX = 16>
 __device__ inline void store_C(const typename Prec<P>::Acc (&C)[MT], typename Prec<P>::T* dst,
                                int rmax, typename Prec<P>::T scale, int lane) {
+  static_assert(CMAX <= RS, "stored columns fit the row stride");
 #pragma unroll
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int r = 16 * t + Prec<P>::crow(lane, i);
-      if (r < rmax) dst[r * RS + (lane & 15)] = scale * C[t][i];
+      if (r < rmax && (CMAX == 16 || (lane & 15) < CMAX)) dst[r * RS + (lane & 15)] = scale * C[t][i];
     }
 }
 
