@@ -204,8 +204,17 @@ __global__ __launch_bounds__(64) void k_adj_lift(AdjArgs<P> A) {
     store_C<P, MT, 16>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
 }
 
+// Derivatives D^i of the predictor in registers (one LDS buffer, which also
+// takes the time-point states), or all of them in LDS: as in the forward
+// kernel, except FP64, whose adjoint registers would not fit.
+template <int N, int P> struct AdjRegs {
+  static constexpr bool value = P != PREC_F64 && N <= 3;
+  static constexpr int ND = value ? 1 : N + 1;
+};
+
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AdjRegs<N, P>::value ? 3 : 1)))
+void k_adj_volume(AdjArgs<P> A) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
@@ -213,26 +222,51 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   const StepArgs<P>& a = A.s;
   constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
-  constexpr int R = PredLDS<N, P>::R, DS = PredLDS<N, P>::DS;
+  constexpr bool REGS = AdjRegs<N, P>::value;
+  constexpr int ND = AdjRegs<N, P>::ND;
+  // with the derivatives in registers the time-point buffer W is unused and
+  // A*_e may share its storage
+  using SL = PredLDS<N, P, ND, REGS>;
+  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
   static_assert(DS == 16, "adjoint states are exchanged with HBM row by row");
-  __shared__ PredLDS<N, P> S;
+  __shared__ SL S;
   // sLD[i] = dJ/dD^i; sLD[0] starts as lambda^{n+1} (the identity path) and
   // ends as lambda^n minus the nodal path of the tangent and source at t_n
   __shared__ T sLD[N + 1][KPL * DS];
-  __shared__ T sLds[48];
+  T dreg[REGS ? (N + 1) * DPL : 1];
   T* const sX = S.B;
   T* const sLam = sLD[0];
-  T* const sLA = S.B;   // dJ/dA*_e, between the CK reversal and the t_n pass
-
+  T* const sLA = S.B;     // dJ/dA*_e, between the CK reversal and the t_n pass
+  T* const sLds = S.Acc;  // its cell-average cotangent (the average itself is spent)
+  // time-point state, then dJ/dU_z; at the end the nodal path at t_n
+  T* const sZ = REGS ? S.D[0] : S.W;
   const int lane = threadIdx.x;
+  // D^i[idx] for idx = lane + 64 j
+  auto Dv = [&](int i, int j) -> T {
+    if constexpr (REGS)
+      return dreg[i * DPL + j];
+    else
+      return S.D[i][lane + 64 * j];
+  };
+  // D^i to the LDS buffer read by the matrix cores (a no-op when all are there)
+  auto Dlds = [&](int i) -> const T* {
+    if constexpr (REGS) {
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) S.D[0][lane + 64 * j] = dreg[i * DPL + j];
+      return S.D[0];
+    } else {
+      return S.D[i];
+    }
+  };
+
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   if (A.Dkept)
-    predictor_restore<N, P>(a, e, S, m, A.Dkept, A.Akept, lane);
+    predictor_restore<N, P, ND, REGS>(a, e, S, m, A.Dkept, A.Akept, lane, dreg);
   else
-    predictor_stage<N, P, N + 1, false>(a, e, S, m, lane, nullptr);
+    predictor_stage<N, P, ND, REGS, REGS>(a, e, S, m, lane, dreg);
   for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
   for (int i = lane; i < N * KPL * DS; i += 64) (&sLD[1][0])[i] = T(0);
   T Ji[9];
@@ -294,11 +328,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     const T h = a.tau[z] * (T)a.dt;
 #pragma unroll
     for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    for (int idx = lane; idx < KPL * DS; idx += 64) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
       T v = T(0);
 #pragma unroll
-      for (int i = 0; i <= N; ++i) v += cz[i] * S.D[i][idx];
-      S.W[idx] = v;
+      for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
+      sZ[lane + 64 * j] = v;
     }
     __syncthreads();
     const T g = a.gamma[z];
@@ -308,7 +343,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     for (int c = 0; c < NCH; ++c) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, S.W, C, lane);
+      wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, sZ, C, lane);
       store_C<P, 4>(C, sX, 64, T(1), lane);
       __syncthreads();
       const int q = 64 * c + lane;
@@ -335,12 +370,12 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
       wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cl, lane);
       __syncthreads();
     }
-    // S.W (the time-point state) is free now: dJ/dU_z goes there
-    store_C<P, MT, DS>(Cl, S.W, KPL, T(1), lane);
+    // the time-point state is spent: dJ/dU_z goes there
+    store_C<P, MT, DS>(Cl, sZ, KPL, T(1), lane);
     __syncthreads();
     const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
     for (int idx = lane; idx < KPL * DS; idx += 64) {
-      const T v = S.W[idx] + lz[idx];
+      const T v = sZ[idx] + lz[idx];
 #pragma unroll
       for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
     }
@@ -353,7 +388,9 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   Acc CA[3];
   zero_C<P, 3>(CA);
   __syncthreads();
+#pragma unroll
   for (int i = N; i >= 1; --i) {
+    const T* Dm = Dlds(i - 1);
 #pragma unroll
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[MT];
@@ -368,7 +405,7 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
 #pragma unroll
       for (int st = 0; st < KSL; ++st) {
         const T av = S.B[(ee * KPL + KS * st + (lane >> 4)) * R + (lane & 15)];
-        CA[ee] = PR::mma(av, PR::template loadB<DS>(S.D[i - 1], st, lane), CA[ee]);
+        CA[ee] = PR::mma(av, PR::template loadB<DS>(Dm, st, lane), CA[ee]);
       }
     // dJ/dD^{i-1}[l][q] += sum_e sum_p dJ/dY_e[l][p] A*_e[p][q]   (K = p, 3 steps)
     {
@@ -443,11 +480,13 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
   T lt[6][7];
   Acc Cu[MT];
   zero_C<P, MT>(Cu);
+  const T* D0 = Dlds(0);
+  __syncthreads();
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, S.D[0], C, lane);
+    wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, D0, C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     const int q = 64 * c + lane;
@@ -474,11 +513,11 @@ __global__ __launch_bounds__(64) void k_adj_volume(AdjArgs<P> A) {
     wave_gemm<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cu, lane);
     __syncthreads();
   }
-  store_C<P, MT, DS>(Cu, S.W, KPL, T(1), lane);
+  store_C<P, MT, DS>(Cu, sZ, KPL, T(1), lane);
   __syncthreads();
   // lambda^n = (lambda^{n+1} + dJ/dD^0, held in sLD[0]) + nodal path
   T* out = A.lamOut + (size_t)e * KPL * 16;
-  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLD[0][idx] + S.W[idx];
+  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLD[0][idx] + sZ[idx];
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
     double gf = 0.0;

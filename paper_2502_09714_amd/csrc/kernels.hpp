@@ -307,22 +307,30 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
 
 // The predictor's results kept by an earlier launch of k_predict_volume on the
 // same state (D^1..D^N and the cell-averaged tangent): load them instead of
-// recomputing them.  Leaves S as predictor_stage does, except S.R_ and S.W.
-template <int N, int P>
-__device__ inline void predictor_restore(const StepArgs<P>& a, long long e, PredLDS<N, P>& S,
+// recomputing them.  Leaves S (and dreg) as predictor_stage does, except S.R_.
+template <int N, int P, int ND, bool REGS, bool AW>
+__device__ inline void predictor_restore(const StepArgs<P>& a, long long e,
+                                         PredLDS<N, P, ND, AW>& S,
                                          const MatP<typename Prec<P>::T>& m,
                                          const typename Prec<P>::T* Dk,
-                                         const typename Prec<P>::T* Ak, int lane) {
+                                         const typename Prec<P>::T* Ak, int lane,
+                                         typename Prec<P>::T* dreg) {
   using T = typename Prec<P>::T;
+  using SL = PredLDS<N, P, ND, AW>;
   constexpr int L = Dims<N>::L;
-  constexpr int KPL = round_up(L, Prec<P>::KS), DS = PredLDS<N, P>::DS;
-  for (int i = lane; i < KPL * DS; i += 64) {
-    S.D[0][i] = T(0);
-    S.W[i] = T(0);
-  }
+  constexpr int KPL = SL::KPL, DS = SL::DS, DPL = SL::DPL;
+  static_assert(REGS ? ND == 1 : ND == N + 1, "one buffer with register copies, or all");
+  for (int i = lane; i < KPL * DS; i += 64) S.D[0][i] = T(0);
   const T* U9 = a.U9 + e * 9 * L;
   const T* De = Dk + (size_t)e * N * KPL * 16;
-  for (int i = lane; i < N * KPL * 16; i += 64) (&S.D[1][0])[i] = De[i];
+  if constexpr (REGS) {
+#pragma unroll
+    for (int i = 1; i <= N; ++i)
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) dreg[i * DPL + j] = De[(i - 1) * KPL * 16 + lane + 64 * j];
+  } else {
+    for (int i = lane; i < N * KPL * 16; i += 64) (&S.D[1][0])[i] = De[i];
+  }
   if (lane < 48) S.Acc[lane] = Ak[e * 48 + lane];
   if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
   __syncthreads();
@@ -332,6 +340,10 @@ __device__ inline void predictor_restore(const StepArgs<P>& a, long long e, Pred
   }
   build_Astar<N, P>(S, m, lane);
   __syncthreads();
+  if constexpr (REGS) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) dreg[j] = S.D[0][lane + 64 * j];
+  }
 }
 
 // LDS derivative buffers of the forward predictor: one plus registers up to
