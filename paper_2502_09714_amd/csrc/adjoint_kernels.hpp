@@ -49,8 +49,12 @@ template <int P> struct AdjArgs {
 // both traces, written to gtr[face][side][z][Ns][10] (lifted by k_adj_volume),
 // and of both sides' mu0, summed over the face points with their weights into
 // gmuf[face][side].
+// FP64: two wavefronts per SIMD at the price of a few spilled registers (the
+// unconstrained form needs more than one wavefront's share of the register
+// file); FP32 keeps its registers (forcing four spills far more).
 template <int N, int P>
-__global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P == PREC_F64 && N <= 3 ? 2 : 1)))
+void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A, const int* faces,
   const StepArgs<P>& a = A.s;
   constexpr int L = DM::L, Ns = DM::Ns, Nt = DM::Nt, NST = DM::NST;
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int R = Lds<T>::RS;
+  constexpr int R = 11;   // traces keep the 10 quantities (odd stride: no bank conflicts)
   constexpr int TS = NST * 16 * R;
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
@@ -81,13 +85,13 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A, const int* faces,
     Acc C[NST];
     zero_C<P, NST>(C);
     wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
-    store_C<P, NST>(C, sTm + z * TS, Ns, T(1), lane);
+    store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
   }
   {
     Acc C[NST];
     zero_C<P, NST>(C);
     wave_gemm<P, NST, KSL, 16>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
-    store_C<P, NST>(C, sLm, Ns, T(1), lane);
+    store_C<P, NST, R, 10>(C, sLm, Ns, T(1), lane);
   }
   long long nb = -1;
   int nf = 0;
@@ -100,12 +104,12 @@ __global__ __launch_bounds__(64) void k_adj_face(AdjArgs<P> A, const int* faces,
       Acc C[NST];
       zero_C<P, NST>(C);
       wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, C, lane);
-      store_C<P, NST>(C, sTp + z * TS, Ns, T(1), lane);
+      store_C<P, NST, R, 10>(C, sTp + z * TS, Ns, T(1), lane);
     }
     Acc C[NST];
     zero_C<P, NST>(C);
     wave_gemm<P, NST, KSL, 16>(Fn, A.lam + (size_t)nb * KPL * 16, C, lane);
-    store_C<P, NST>(C, sLp, Ns, T(1), lane);
+    store_C<P, NST, R, 10>(C, sLp, Ns, T(1), lane);
   }
   __syncthreads();
   T n[3];
