@@ -547,33 +547,32 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   const int kind = conn_kind(w), sp = conn_perm(w);
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  // both sides' traces in one pass, so that the loads of both time-point
+  // states are in flight together (a boundary face evaluates its own side
+  // twice and uses the first)
+  const bool inner = kind == 0;
+  const long long nb = inner ? (long long)(of >> 2) : e;
+  const int nf = inner ? (of & 3) : f, sq = inner ? conn_nperm(w) : sp;
   const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+  const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
+  const typename PR::AF* Fn = a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64;
+#pragma unroll
   for (int z = 0; z < Nt; ++z) {
-    Acc C[NST];
+    Acc C[NST], Cn[NST];
     zero_C<P, NST>(C);
-    wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64, Uze + z * KPL * 16,
-                               C, lane);
+    zero_C<P, NST>(Cn);
+    wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
+    wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, Cn, lane);
     store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
-  }
-  long long nb = -1;
-  if (kind == 0) {
-    nb = of >> 2;
-    const int nf = of & 3, sq = conn_nperm(w);
-    const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
-    for (int z = 0; z < Nt; ++z) {
-      Acc C[NST];
-      zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64,
-                                 Uzn + z * KPL * 16, C, lane);
-      store_C<P, NST, R, 10>(C, sTp + z * TS, Ns, T(1), lane);
-    }
+    store_C<P, NST, R, 10>(Cn, sTp + z * TS, Ns, T(1), lane);
   }
   __syncthreads();
   T n[3];
   n[0] = (T)a.fgeo[(e * 4 + f) * 4 + 0];
   n[1] = (T)a.fgeo[(e * 4 + f) * 4 + 1];
   n[2] = (T)a.fgeo[(e * 4 + f) * 4 + 2];
-  const MatP<T> mp = kind == 0 ? load_mat<T>(a.mat + nb * 8) : m;
+  const MatP<T> mp = load_mat<T>(a.mat + nb * 8);
   for (int idx = lane; idx < Ns * Nt; idx += 64) {
     const int z = idx / Ns, i = idx - z * Ns;
     T* um = sTm + z * TS + i * R;
@@ -622,39 +621,69 @@ __global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fm
   constexpr int FS = KPN * R > MT * 16 * R ? KPN * R : MT * 16 * R;
   __shared__ T sF[FS];
 
+  constexpr int FPL = (Ns * 10 + 63) / 64;   // flux values per lane and face
+  constexpr int WPL = (9 * L + 63) / 64;     // partial-update values per lane
+
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
+  // every HBM load is issued before the first use: the four faces' fluxes
+  // (gathered by face) and the partial update
+  T fv[4][FPL], sc[4];
+  int sp[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int fm = fmap[e * 4 + f];
+    sp[f] = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
+    sc[f] = (T)((fm & 1 ? -1.0 : 1.0) * a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
+    const T* fl = fflux + (size_t)(fm >> 1) * Ns * 10;
+#pragma unroll
+    for (int j = 0; j < FPL; ++j) {
+      const int idx = lane + 64 * j;
+      fv[f][j] = idx < Ns * 10 ? fl[idx] : T(0);
+    }
+  }
+  T* W9 = a.W9 + e * 9 * L;
+  T wv[WPL];
+#pragma unroll
+  for (int j = 0; j < WPL; ++j) {
+    const int idx = lane + 64 * j;
+    wv[j] = idx < 9 * L ? W9[idx] : T(0);
+  }
+  const double wa = lane < L ? a.Wa[e * L + lane] : 0.0;
   for (int i = lane; i < FS; i += 64) sF[i] = T(0);
   Acc Fc[MT];
   zero_C<P, MT>(Fc);
+#pragma unroll
   for (int f = 0; f < 4; ++f) {
-    const int fm = fmap[e * 4 + f];
-    const long long fid = fm >> 1;
-    const int sp = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
-    const T sc = (T)((fm & 1 ? -1.0 : 1.0) * a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
-    const T* fl = fflux + (size_t)fid * Ns * 10;
     __syncthreads();
-    for (int idx = lane; idx < Ns * 10; idx += 64) {
-      const int i = idx / 10, k = idx - i * 10;
-      sF[i * R + k] = sc * fl[idx];
+#pragma unroll
+    for (int j = 0; j < FPL; ++j) {
+      const int idx = lane + 64 * j;
+      if (idx < Ns * 10) {
+        const int i = idx / 10, k = idx - i * 10;
+        sF[i * R + k] = sc[f] * fv[f][j];
+      }
     }
     __syncthreads();
-    wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sF, Fc, lane);
+    wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp[f]) * MT * KSN * 64, sF, Fc, lane);
   }
   __syncthreads();
   store_C<P, MT>(Fc, sF, L, T(1), lane);
   __syncthreads();
-  T* W9 = a.W9 + e * 9 * L;
   bool bad = false;
-  for (int idx = lane; idx < 9 * L; idx += 64) {
-    const int p = idx / L, l = idx - p * L;
-    const T v = W9[idx] - sF[l * R + p];
-    bad |= !isfinite(v);
-    W9[idx] = v;
+#pragma unroll
+  for (int j = 0; j < WPL; ++j) {
+    const int idx = lane + 64 * j;
+    if (idx < 9 * L) {
+      const int p = idx / L, l = idx - p * L;
+      const T v = wv[j] - sF[l * R + p];
+      bad |= !isfinite(v);
+      W9[idx] = v;
+    }
   }
   if (lane < L) {
-    const double v = a.Wa[e * L + lane] - (double)sF[lane * R + 9];
+    const double v = wa - (double)sF[lane * R + 9];
     bad |= !isfinite(v);
     a.Wa[e * L + lane] = v;
   }
