@@ -79,37 +79,28 @@ void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
   const int kind = conn_kind(w), sp = conn_perm(w);
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  // both sides' traces in one pass (a boundary face evaluates its own side
+  // twice and uses the first), so that all their loads are in flight together
+  const bool inner = kind == 0;
+  const long long nb = inner ? (long long)(of >> 2) : e;
+  const int nf = inner ? (of & 3) : f;
   const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
+  const typename PR::AF* Fn =
+      a.Fpk + (size_t)(nf * 6 + (inner ? conn_nperm(w) : sp)) * NST * KSL * 64;
   const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
-  for (int z = 0; z < Nt; ++z) {
-    Acc C[NST];
+  const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+#pragma unroll
+  for (int z = 0; z <= Nt; ++z) {
+    // z < Nt: time-point states; z = Nt: lambda^{n+1}
+    const T* Be = z < Nt ? Uze + z * KPL * 16 : A.lam + (size_t)e * KPL * 16;
+    const T* Bn = z < Nt ? Uzn + z * KPL * 16 : A.lam + (size_t)nb * KPL * 16;
+    Acc C[NST], Cn[NST];
     zero_C<P, NST>(C);
-    wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
-    store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
-  }
-  {
-    Acc C[NST];
-    zero_C<P, NST>(C);
-    wave_gemm<P, NST, KSL, 16>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
-    store_C<P, NST, R, 10>(C, sLm, Ns, T(1), lane);
-  }
-  long long nb = -1;
-  int nf = 0;
-  if (kind == 0) {
-    nb = of >> 2;
-    nf = of & 3;
-    const typename PR::AF* Fn = a.Fpk + (size_t)(nf * 6 + conn_nperm(w)) * NST * KSL * 64;
-    const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
-    for (int z = 0; z < Nt; ++z) {
-      Acc C[NST];
-      zero_C<P, NST>(C);
-      wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, C, lane);
-      store_C<P, NST, R, 10>(C, sTp + z * TS, Ns, T(1), lane);
-    }
-    Acc C[NST];
-    zero_C<P, NST>(C);
-    wave_gemm<P, NST, KSL, 16>(Fn, A.lam + (size_t)nb * KPL * 16, C, lane);
-    store_C<P, NST, R, 10>(C, sLp, Ns, T(1), lane);
+    zero_C<P, NST>(Cn);
+    wave_gemm<P, NST, KSL, 16>(Fe, Be, C, lane);
+    wave_gemm<P, NST, KSL, 16>(Fn, Bn, Cn, lane);
+    store_C<P, NST, R, 10>(C, z < Nt ? sTm + z * TS : sLm, Ns, T(1), lane);
+    store_C<P, NST, R, 10>(Cn, z < Nt ? sTp + z * TS : sLp, Ns, T(1), lane);
   }
   __syncthreads();
   T n[3];
@@ -189,15 +180,32 @@ __global__ __launch_bounds__(64) void k_adj_lift(AdjArgs<P> A) {
   Acc Cz[Nt][MT];
 #pragma unroll
   for (int z = 0; z < Nt; ++z) zero_C<P, MT>(Cz[z]);
-  for (int f = 0; f < 4; ++f) {
+  // the next face's cotangents are loaded while this face's are lifted
+  constexpr int GPL = (Nt * Ns * 10 + 63) / 64;
+  T gv[GPL];
+  auto load_face = [&](int f) {
     const int fm = A.fmap[e * 4 + f];
-    const int sp = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
     const T* g = A.gtr + ((size_t)(fm >> 1) * 2 + (fm & 1)) * Nt * Ns * 10;
-    __syncthreads();
-    for (int idx = lane; idx < Nt * Ns * 10; idx += 64) {
-      const int zi = idx / 10, k = idx - zi * 10, z = zi / Ns, i = zi - z * Ns;
-      sG[z * GB + i * R + k] = g[idx];
+#pragma unroll
+    for (int j = 0; j < GPL; ++j) {
+      const int idx = lane + 64 * j;
+      gv[j] = idx < Nt * Ns * 10 ? g[idx] : T(0);
     }
+  };
+  load_face(0);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int sp = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < GPL; ++j) {
+      const int idx = lane + 64 * j;
+      if (idx < Nt * Ns * 10) {
+        const int zi = idx / 10, k = idx - zi * 10, z = zi / Ns, i = zi - z * Ns;
+        sG[z * GB + i * R + k] = gv[j];
+      }
+    }
+    if (f < 3) load_face(f + 1);
     __syncthreads();
 #pragma unroll
     for (int z = 0; z < Nt; ++z)
