@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--precisions", default="fp32,fp64,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=6)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--adjoint-precisions", default="fp32,fp64",
                     help="precisions whose checkpointed adjoint is timed ('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
