@@ -98,7 +98,8 @@ __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
 // The time-point buffer W and A*_e: separate, or (AW) sharing storage, which
 // the forward kernel can afford because it copies A*_e to registers before
-// the first time-point state is formed.
+// the first time-point state is formed (and the adjoint's register form,
+// which puts its time-point states elsewhere).
 template <class T, int NW, bool AW> struct PredWA {
   T W[NW];                // time-point state / scratch
   T A[300];               // A*_e (3 x 10 x 10)
@@ -522,7 +523,7 @@ void k_predict_volume(StepArgs<P> a) {
 // boundary) flux with the normal of the face's first element, time quadrature.
 // Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
 template <int N, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 4 ? 1 : (P == PREC_F64 ? 4 : 6))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 4 ? 1 : (P == PREC_F64 ? 4 : 7))))
 void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux) {
   using PR = Prec<P>;
   using T = typename PR::T;
