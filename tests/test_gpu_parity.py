@@ -131,6 +131,44 @@ def test_sources_and_receivers():
     sim.close()
 
 
+@pytest.fixture(scope="module")
+def finite_fault_oracle():
+    """c5 recipe cut to 4^3 cubes x 6 = 384 tets at its degree N = 4: the 3 km
+    gradient basin and the 64 subfault point sources (Gaussian moment
+    functions), started at the earliest onset so that every step injects."""
+    w = make_workload("c5", n=4, N=4)
+    assert w.N == 4 and len(w.sources["xyz"]) == 64
+    S = oracle_from(w)
+    U0 = S.project(w.ic)
+    src = PointSources(S, **w.sources)
+    rec = Receivers(S, w.receivers)
+    t0 = float(np.min(w.sources["t_onset"]))
+    U, t, seis = U0, t0, []
+    for _ in range(3):
+        U = S.step(U) + src.increment(t, t + S.dt)
+        t += S.dt
+        seis.append(rec.sample(U).numpy())
+    return w, U0, t0, U, t, np.stack(seis)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_finite_fault_sources(finite_fault_oracle, prec, tol):
+    w, U0, t0, U, t, want = finite_fault_oracle
+    sim = _api().from_workload(w, prec)
+    assert sim.nrec == len(w.receivers)
+    sim.set_state(_to_lib(U0))
+    sim.set_time(t0)
+    sim.clear_seismograms()
+    sim.step(3)
+    r = rel(sim.get_state(), _to_lib(U))
+    assert r["all"] < tol, r
+    got = sim.get_seismograms()
+    assert got.shape == want.shape and np.abs(want).max() > 0
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < tol
+    assert abs(sim.get_time() - t) < 1e-12
+    sim.close()
+
+
 def test_diagnostics():
     w, S, sim = _setup("c2", n=3, N=3)
     U = S.project(w.ic)
