@@ -161,10 +161,14 @@ def _pulses_ic(mesh, rng, alpha0, npulse=32, width=50.0, amax=1e-4):
     dirs = dirs / fro[:, None]
 
     def ic(x, elem):
-        out = np.zeros((x.shape[0], 10))
-        for c, a, d in zip(centres, amps, dirs):
-            r2 = ((x - c[None, :])**2).sum(1)
-            out[:, :6] += (a * np.exp(-r2 / (2.0 * width * width)))[:, None] * d[None, :]
+        # pulse profiles (points x pulses), then one product with the directions
+        xt = np.ascontiguousarray(np.asarray(x, dtype=np.float64).T)
+        g = np.empty((xt.shape[1], npulse))
+        for k in range(npulse):
+            r2 = (xt[0] - centres[k, 0])**2 + (xt[1] - centres[k, 1])**2 + (xt[2] - centres[k, 2])**2
+            g[:, k] = amps[k] * np.exp(r2 * (-1.0 / (2.0 * width * width)))
+        out = np.zeros((xt.shape[1], 10))
+        out[:, :6] = g @ dirs
         out[:, 9] = alpha0[elem]
         return out
     return ic
