@@ -160,7 +160,7 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
  * every launch while profiling is on.  dgd_get_kernel_times synchronises,
  * returns the summed milliseconds and launch counts of the kernel classes
  * {0: predictor + volume, 1: face fluxes, 2: sources, 3: receivers,
- *  4: adjoint's predictor recomputation, 5: adjoint faces, 6: adjoint
+ *  4: adjoint's predictor recomputation, 5: adjoint faces and their lift, 6: adjoint
  *  volume + predictor, 7: adjoint receivers, 8: lift of the face fluxes +
  *  update}
  * since the last call, and resets them. */
