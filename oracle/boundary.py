@@ -2,7 +2,8 @@
 
 On domain boundaries only the isotropic part of the CDM Jacobian is kept: the
 effective matrices B^{d,eff} in effective Lame parameters (Eqs. matrix_Beff_1..3,
-effective-cdb).  The paper's printed matrices carry typos; readings used here:
+effective-cdb; for the IVM law the caller passes Eq. effective-ivm).  The paper's
+printed matrices carry typos; readings used here:
 
 * the alpha row/column of B^{d,eff} is zero (alpha carries no flux; the
   printed 1 in entry (10,10) would contradict the zero eigenvalue of Lambda);
@@ -129,8 +130,9 @@ def _frame(u, n):
     return T, up
 
 
-def absorbing_flux(u, n, mat, alpha_max, i2_min=I2_MIN_F64):
-    lam, mu = effective_lame(u, mat, alpha_max, i2_min)
+def absorbing_flux(u, n, mat, alpha_max, i2_min=I2_MIN_F64, lame=None):
+    """lame: the rheology's effective Lame parameters (default: CDM)."""
+    lam, mu = (lame or effective_lame)(u, mat, alpha_max, i2_min)
     T, up = _frame(u, n)
     R, ld = R_matrix(lam, mu, mat["rho"])
     lplus = torch.clamp(ld, min=0.0)
@@ -139,8 +141,9 @@ def absorbing_flux(u, n, mat, alpha_max, i2_min=I2_MIN_F64):
     return (T @ fp[..., None])[..., 0]
 
 
-def free_surface_flux(u, n, mat, alpha_max, i2_min=I2_MIN_F64):
-    lam, mu = effective_lame(u, mat, alpha_max, i2_min)
+def free_surface_flux(u, n, mat, alpha_max, i2_min=I2_MIN_F64, lame=None):
+    """lame: the rheology's effective Lame parameters (default: CDM)."""
+    lam, mu = (lame or effective_lame)(u, mat, alpha_max, i2_min)
     T, up = _frame(u, n)
     R, _ = R_matrix(lam, mu, mat["rho"])
     C = C_matrix(lam, mu)

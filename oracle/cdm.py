@@ -83,7 +83,12 @@ def energy_density(u, mat, alpha_max, i2_min=I2_MIN_F64):
 
 def flux(u, mat, alpha_max, i2_min=I2_MIN_F64):
     """F^d_p (..., 3, 10), Eq. nonlinear hyper pdes."""
-    sig = stress(u, mat, alpha_max, i2_min)
+    return flux_of_stress(stress(u, mat, alpha_max, i2_min), u, mat["rho"])
+
+
+def flux_of_stress(sig, u, rho):
+    """F^d_p (..., 3, 10) of Eq. nonlinear hyper pdes for a given stress (any
+    rheology): strain rows from the velocity, velocity rows -sigma_id/rho."""
     v = u[..., 6:9]
     zero = torch.zeros_like(v[..., 0])
     rows = []
@@ -97,7 +102,7 @@ def flux(u, mat, alpha_max, i2_min=I2_MIN_F64):
                 val = val - 0.5 * v[..., j]
             comp.append(val)
         for i in range(3):
-            comp.append(-sig[..., SYM[i][d]] / mat["rho"])
+            comp.append(-sig[..., SYM[i][d]] / rho)
         comp.append(zero)
         rows.append(torch.stack(comp, dim=-1))
     return torch.stack(rows, dim=-2)

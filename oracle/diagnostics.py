@@ -10,7 +10,8 @@ formula; readings used here:
 * damage-only shear-wave-speed change of element m:
   dc_s/c_s = sqrt(max(mu0 + abar xi0 gamma_r, 0) / mu0) - 1,
   abar the clamped cell mean of alpha (mu0 + alpha xi0 gamma_r is the
-  damaged shear modulus of the stress law).
+  damaged shear modulus of the stress law); for the IVM law
+  dc_s/c_s = sqrt(1 - abar) - 1 (shear modulus (1 - alpha) mu0).
 """
 import math
 
@@ -35,6 +36,9 @@ def wavespeed_change(solver, U):
     phi0_int = float(solver.ref.wq @ solver.ref.V[:, 0])
     abar = 6.0 * phi0_int * U[:, 0, 9]
     abar = torch.clamp(abar, 0.0, solver.alpha_max)
+    if solver.law.__name__.endswith("ivm"):
+        # shear modulus (1 - alpha) mu0 (Eq. effective-ivm)
+        return torch.sqrt(1.0 - abar) - 1.0
     mu0 = solver.mat["mu0"]
     mud = torch.clamp(mu0 + abar * solver.mat["xi0"] * solver.mat["gamma_r"], min=0.0)
     return torch.sqrt(mud / mu0) - 1.0

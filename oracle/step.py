@@ -1,4 +1,4 @@
-"""One ADER-DG step of the CDM system (oracle), Section 2.2 and Appendix A.
+"""One ADER-DG step of the CDM (or IVM) system (oracle), Section 2.2 and Appendix A.
 
 Modal coefficients U[m, l, p] (element m, mode l, quantity p) of the expansion
 u^h_p = sum_l U_lp phi_l (Eq. modal dg space).  One global time step
@@ -46,16 +46,19 @@ class OracleSolver:
     """Plain FP64 CPU reference solver for one workload."""
 
     def __init__(self, xyz, tets, face_tag, periodic_map, material, N, dt,
-                 alpha_max=0.5, i2_min=cdm.I2_MIN_F64, llf_speed=None):
+                 alpha_max=0.5, i2_min=cdm.I2_MIN_F64, llf_speed=None, law=cdm):
         self.N = N
+        # the rheology's pointwise law: oracle.cdm (Eq. cdb-model) or
+        # oracle.ivm (Eq. ivm-model)
+        self.law = law
         # largest eigenvalue of B_n (Eq. rusanov-flux); replaceable by an
         # equal, differentiable form (oracle.adjoint)
-        self.llf_speed = cdm.llf_speed if llf_speed is None else llf_speed
+        self.llf_speed = law.llf_speed if llf_speed is None else llf_speed
         self.ref = RefElement(N)
         self.mesh = OracleMesh(xyz, tets, face_tag, periodic_map, self.ref)
         self.E = self.mesh.E
         self.mat = {k: torch.as_tensor(np.asarray(material[k], dtype=np.float64))
-                    for k in cdm.MAT_KEYS}
+                    for k in law.MAT_KEYS}
         self.dt = float(dt)
         self.alpha_max = float(alpha_max)
         self.i2_min = float(i2_min)
@@ -87,14 +90,14 @@ class OracleSolver:
         am, i2 = self.alpha_max, self.i2_min
         mat_q = self._mat(extra_dims=1)
         uq = torch.einsum("ql,mlp->mqp", ref.V, U)
-        B = cdm.flux_jacobian(uq, mat_q, am, i2)                      # (E,Q,3,10,10)
+        B = self.law.flux_jacobian(uq, mat_q, am, i2)                 # (E,Q,3,10,10)
         Bbar = torch.einsum("q,mqdij->mdij", ref.wq, B) / ref.wq.sum()
         Astar = torch.einsum("med,mdij->meij", m.Jinv, Bbar)           # (E,3,10,10)
         D = [U]
         for i in range(1, self.N + 1):
             rhs = -torch.einsum("ekl,mlq,mepq->mkp", ref.K, D[i - 1], Astar)
             if i == 1:
-                r = cdm.r_alpha(uq, mat_q, am, i2)                    # (E,Q)
+                r = self.law.r_alpha(uq, mat_q, am, i2)               # (E,Q)
                 src = torch.einsum("ql,q,mq->ml", ref.V, ref.wq, r)
                 rhs = rhs.clone()
                 rhs[..., 9] = rhs[..., 9] + src
@@ -124,9 +127,9 @@ class OracleSolver:
         Sint = 0.0
         for z in range(ref.Nt):
             u = torch.einsum("ql,mlp->mqp", ref.V, Uz[z])
-            F = cdm.flux(u, mat_q, am, i2)                            # (E,Q,3,10)
+            F = self.law.flux(u, mat_q, am, i2)                       # (E,Q,3,10)
             Fmod = torch.einsum("lq,mqdp->mdlp", ref.P, F)            # modal flux
-            S = cdm.r_alpha(u, mat_q, am, i2)
+            S = self.law.r_alpha(u, mat_q, am, i2)
             Smod = torch.einsum("lq,mq->ml", ref.P, S)
             Fint = Fint + ref.gamma[z] * Fmod
             Sint = Sint + ref.gamma[z] * Smod
@@ -156,8 +159,8 @@ class OracleSolver:
                 for z in range(ref.Nt):
                     uM = torch.einsum("mil,mlp->mip", m.Fface[me, f], Uz[z][me])
                     uP = torch.einsum("mil,mlp->mip", m.Fnbr[me, f], Uz[z][nb])
-                    FM = torch.einsum("mid,midp->mip", n, cdm.flux(uM, mat_m, am, i2))
-                    FP = torch.einsum("mid,midp->mip", n, cdm.flux(uP, mat_p, am, i2))
+                    FM = torch.einsum("mid,midp->mip", n, self.law.flux(uM, mat_m, am, i2))
+                    FP = torch.einsum("mid,midp->mip", n, self.law.flux(uP, mat_p, am, i2))
                     ubar = 0.5 * (uM + uP)
                     C = torch.maximum(self.llf_speed(ubar, n, mat_m, am, i2),
                                       self.llf_speed(ubar, n, mat_p, am, i2))
@@ -174,7 +177,10 @@ class OracleSolver:
                 acc = 0.0
                 for z in range(ref.Nt):
                     uM = torch.einsum("mil,mlp->mip", m.Fface[me, f], Uz[z][me])
-                    acc = acc + ref.gamma[z] * fn(uM, n, mat_m, am, i2)
+                    # effective Lame parameters: the law's own (IVM) or the
+                    # CDM ones of oracle.boundary
+                    acc = acc + ref.gamma[z] * fn(uM, n, mat_m, am, i2,
+                                                  lame=getattr(self.law, "effective_lame", None))
                 out[me, f] = acc
         return out
 
@@ -202,7 +208,9 @@ class OracleSolver:
 
 
 def from_workload(w, **kw):
-    """OracleSolver for a :class:`workloads.Workload`."""
+    """OracleSolver for a :class:`workloads.Workload` (its rheology's law)."""
+    from . import ivm
     m = w.mesh
+    kw.setdefault("law", ivm if getattr(w, "rheology", "cdm") == "ivm" else cdm)
     return OracleSolver(m["xyz"], m["tets"], m["face_tag"], m["periodic_map"],
                         w.material, w.N, w.dt, alpha_max=w.alpha_max, **kw)
