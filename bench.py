@@ -213,6 +213,24 @@ def cpu_baseline(name, n_sample, steps):
                       f"{steps} steps after one untimed step, {dt:.1f} s, torch float64 CPU"}
 
 
+def run_ivm(args, precs, dofs):
+    """Step timing of the benchmark workload with the IVM law, per precision."""
+    from workloads import make_workload
+    wi = make_workload(args.workload, n=args.n, rheology="ivm")
+    ri = {p: run_precision(wi, p, args.steps, args.warmup) for p in precs}
+    iv = {"workload": f"{args.workload} with the IVM law", "steps": args.steps}
+    for p in precs:
+        iv[f"{p}_ms_per_step"] = ri[p]["ms_per_step"]
+        iv[f"{p}_dof_updates_per_s"] = dofs * args.steps / ri[p]["seconds"]
+        iv[f"{p}_kernel_ms_per_step"] = {k: ri[p]["kernel_ms"][k] / args.steps
+                                         for k in STEP_KERNELS}
+    if "fp64" in ri:
+        for p in precs:
+            if p != "fp64":
+                iv[f"l2_{p}_vs_fp64_gpu"] = rel_l2(ri[p]["state"], ri["fp64"]["state"])
+    return iv
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +248,8 @@ def main():
     ap.add_argument("--adjoint-workload", default="c4",
                     help="workload of the full-length adjoint timing ('' for none)")
     ap.add_argument("--adjoint-workload-precisions", default="fp32")
+    ap.add_argument("--ivm-precisions", default="fp32,fp64",
+                    help="precisions of the IVM-rheology step timing ('' for none)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -303,6 +323,15 @@ def main():
             if p != "fp64":
                 line[f"speedup_{p}_vs_fp64"] = rate(p) / rate("fp64")
                 line[f"l2_{p}_vs_fp64_gpu"] = rel_l2(res[p]["state"], res["fp64"]["state"])
+    ivm_precs = [q.strip() for q in args.ivm_precisions.split(",") if q.strip()]
+    if ivm_precs:
+        # the same workload with the internal-variable rheology (Eq. ivm-model);
+        # a failure here is reported in the line, not allowed to lose it
+        try:
+            line["ivm"] = run_ivm(args, ivm_precs, dofs)
+        except Exception as exc:          # noqa: BLE001
+            line["ivm"] = {"error": f"{type(exc).__name__}: {exc}"}
+        print(f"ivm: {line['ivm']}", file=sys.stderr, flush=True)
     for p in [q.strip() for q in args.adjoint_precisions.split(",") if q.strip()]:
         a = run_adjoint(w, p, args.steps, args.checkpoint_every)
         print(f"adjoint {p}: {a}", file=sys.stderr, flush=True)

@@ -97,6 +97,20 @@ dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lamb
                             const double* mu0, const double* gamma_r,
                             const double* xi0, const double* Cd);
 
+/* Per-element parameters of the internal-variable rheology (Eq. ivm-model,
+ * Murnaghan terms off), which then replaces the CDM law in every step:
+ *   sigma = (1 - alpha)(lambda0 I1 delta + 2 mu0 eps),
+ *   r_alpha = [lambda0 I1^2/2 + mu0 I2 - gamma_b (alpha/(1 - alpha))^2]
+ *             / (gamma_b tau_b),
+ * alpha clamped to [0, alpha_max] where used; boundary moduli of Eq.
+ * effective-ivm.  Host arrays of ne: density rho, Lame lambda0, mu0, storage
+ * energy scale gamma_b (Pa), damage time scale tau_b (s).  A later
+ * dgd_set_material returns to the CDM law.  The adjoint and dgd_energy are
+ * those of the CDM law and return EINVAL under this one.  EINVAL if rho, mu0,
+ * gamma_b or tau_b <= 0. */
+dgd_status dgd_set_material_ivm(dgd_handle* h, const double* rho, const double* lambda0,
+                                const double* mu0, const double* gamma_b, const double* tau_b);
+
 /* Global time step dt (fixed for the run) and the clamp alpha_max applied to
  * alpha wherever it is used (the stored alpha is never modified). */
 dgd_status dgd_set_params(dgd_handle* h, double dt, double alpha_max);
@@ -152,7 +166,7 @@ dgd_status dgd_clear_seismograms(dgd_handle* h);
  * CDM energy W whose strain derivative is the stress of Eq. cdb-model, and
  * the damage-only shear-wave-speed change per element
  * sqrt(max(mu0 + abar xi0 gamma_r, 0)/mu0) - 1 (abar: clamped cell mean of
- * alpha).  Both synchronise. */
+ * alpha), sqrt(1 - abar) - 1 under the IVM law.  Both synchronise. */
 dgd_status dgd_energy(dgd_handle* h, double* E);
 dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
 

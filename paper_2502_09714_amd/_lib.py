@@ -30,6 +30,7 @@ _SIGS = {
     "dgd_sizes": (ctypes.c_int, [H, c_ip, c_ip, c_ip, c_ip]),
     "dgd_set_mesh": (ctypes.c_int, [H, ctypes.c_int64, c_dp, ctypes.c_int64, c_i64p, c_i8p, c_i64p]),
     "dgd_set_material": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp, c_dp, c_dp]),
+    "dgd_set_material_ivm": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp, c_dp]),
     "dgd_set_params": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double]),
     "dgd_get_quadrature_points": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, c_dp]),
     "dgd_set_state_from_points": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, c_dp]),

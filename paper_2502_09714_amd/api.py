@@ -78,6 +78,12 @@ class Simulation:
         self._chk(self._L.dgd_set_material(self.h, *[_dp(a) for a in arrs]))
         self.material = dict(zip(("rho", "lambda0", "mu0", "gamma_r", "xi0", "Cd"), arrs))
 
+    def set_material_ivm(self, rho, lambda0, mu0, gamma_b, tau_b):
+        """Internal-variable rheology (Eq. ivm-model) in place of the CDM law."""
+        arrs = [_f64(a) for a in (rho, lambda0, mu0, gamma_b, tau_b)]
+        self._chk(self._L.dgd_set_material_ivm(self.h, *[_dp(a) for a in arrs]))
+        self.material = dict(zip(("rho", "lambda0", "mu0", "gamma_b", "tau_b"), arrs))
+
     def set_params(self, dt, alpha_max):
         self._chk(self._L.dgd_set_params(self.h, float(dt), float(alpha_max)))
 
@@ -215,7 +221,11 @@ def from_workload(w, precision="fp64", stream=None, state=True):
     m = w.mesh
     sim.set_mesh(m["xyz"], m["tets"], m["face_tag"], m["periodic_map"])
     mat = w.material
-    sim.set_material(mat["rho"], mat["lambda0"], mat["mu0"], mat["gamma_r"], mat["xi0"], mat["Cd"])
+    if getattr(w, "rheology", "cdm") == "ivm":
+        sim.set_material_ivm(mat["rho"], mat["lambda0"], mat["mu0"], mat["gamma_b"], mat["tau_b"])
+    else:
+        sim.set_material(mat["rho"], mat["lambda0"], mat["mu0"], mat["gamma_r"], mat["xi0"],
+                         mat["Cd"])
     sim.set_params(w.dt, w.alpha_max)
     if state:
         # evaluate the initial condition slice by slice to bound host memory

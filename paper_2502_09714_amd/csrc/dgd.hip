@@ -54,6 +54,7 @@ struct dgd_handle {
   DevBuf faces, fmap, fflux;   // face list (first side, second side), element -> face, face fluxes
   long long nfaces = 0;
   std::vector<double> rho_h;
+  int law = 0;   // 0: continuum damage (Eq. cdb-model), 1: internal variable (Eq. ivm-model)
   // state
   DevBuf U9[2], Ua[2], Uz, flag, scratch;
   int cur = 0;
@@ -333,13 +334,23 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
   using T = typename Prec<P>::T;
   const long long per = (h->ne + 7) / 8;
   const dim3 grid((unsigned)(8 * per)), block(64);
+  const bool ivm = h->law == 1;
   for (long long it = 0; it < nsteps; ++it) {
     StepArgs<P> a = make_args<N, P>(h);
-    timed(h, 0, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
+    timed(h, 0, [&] {
+      if (ivm)
+        hipLaunchKernelGGL((k_predict_volume<N, P, IvmLaw>), grid, block, 0, h->stream, a);
+      else
+        hipLaunchKernelGGL((k_predict_volume<N, P, CdmLaw>), grid, block, 0, h->stream, a);
+    });
     const long long fper = (h->nfaces + 7) / 8;
     timed(h, 1, [&] {
-      hipLaunchKernelGGL((k_face_flux<N, P>), dim3((unsigned)(8 * fper)), block, 0, h->stream, a,
-                         (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
+      if (ivm)
+        hipLaunchKernelGGL((k_face_flux<N, P, IvmLaw>), dim3((unsigned)(8 * fper)), block, 0,
+                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
+      else
+        hipLaunchKernelGGL((k_face_flux<N, P>), dim3((unsigned)(8 * fper)), block, 0,
+                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
     });
     timed(h, 8, [&] {
       hipLaunchKernelGGL((k_lift_update<N, P>), grid, block, 0, h->stream, a,
@@ -844,6 +855,31 @@ dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lamb
   }
   dgd_status s = upload(h, h->mat, m);
   if (s) return s;
+  h->law = 0;
+  h->have_mat = true;
+  return DGD_OK;
+}
+
+dgd_status dgd_set_material_ivm(dgd_handle* h, const double* rho, const double* lambda0,
+                                const double* mu0, const double* gamma_b, const double* tau_b) {
+  if (!h) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  if (!rho || !lambda0 || !mu0 || !gamma_b || !tau_b) return fail(h, DGD_EINVAL, "null array");
+  std::vector<double> m((size_t)h->ne * 8, 0.0);
+  for (long long e = 0; e < h->ne; ++e) {
+    if (!(rho[e] > 0.0) || !(mu0[e] > 0.0)) return fail(h, DGD_EINVAL, "rho and mu0 must be positive");
+    if (!(gamma_b[e] > 0.0) || !(tau_b[e] > 0.0))
+      return fail(h, DGD_EINVAL, "gamma_b and tau_b must be positive");
+    m[e * 8 + 0] = rho[e];
+    m[e * 8 + 1] = lambda0[e];
+    m[e * 8 + 2] = mu0[e];
+    m[e * 8 + 3] = gamma_b[e];
+    m[e * 8 + 5] = 1.0 / (gamma_b[e] * tau_b[e]);
+  }
+  dgd_status s = upload(h, h->mat, m);
+  if (s) return s;
+  h->rho_h.assign(rho, rho + h->ne);
+  h->law = 1;
   h->have_mat = true;
   return DGD_OK;
 }
@@ -1093,6 +1129,7 @@ dgd_status dgd_energy(dgd_handle* h, double* E) {
   if (!h || !E) return DGD_EINVAL;
   if (!h->have_state || !h->have_mat || !h->have_params)
     return fail(h, DGD_ESTATE, "state, material and params needed");
+  if (h->law != 0) return fail(h, DGD_EINVAL, "the energy is that of the continuum-damage law");
   dgd_status s = dalloc(h, h->scratch, (size_t)(h->ne + 1) * sizeof(double));
   if (s) return s;
   double* part = (double*)h->scratch.p;
@@ -1122,7 +1159,7 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* out) {
   if (s) return s;
   hipLaunchKernelGGL(k_wavespeed, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->stream,
                      h->ne, h->ref.L, (const double*)h->Ua[h->cur].p, (const double*)h->mat.p,
-                     h->amax, h->phi0_mean, (double*)h->scratch.p);
+                     h->amax, h->phi0_mean, h->law, (double*)h->scratch.p);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(out, h->scratch.p, (size_t)h->ne * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));
@@ -1184,6 +1221,7 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_o
                             double* grad_mu0, double* grad_cd) {
   if (!h || !lam_next || !lam_out) return DGD_EINVAL;
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
   if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
     return fail(h, DGD_ESTATE, "mesh, material, params and state are needed");
   dgd_status s = alloc_adjoint(h);
@@ -1223,6 +1261,7 @@ dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every
   if (!h) return DGD_EINVAL;
   if (nsteps < 1 || every < 1) return fail(h, DGD_EINVAL, "nsteps >= 1 and every >= 1 needed");
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
   if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
     return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
   release_tape(h);

@@ -163,7 +163,7 @@ __device__ inline void build_Astar(PredLDS<N, P, ND, AW>& S, const MatP<typename
 // (REGS false, ND = N + 1; dreg unused and may be null), or in
 // dreg[i * DPL + j] = D^i[lane + 64 j] (REGS true, ND = 1).  With AW, S.A is
 // not kept past the recursion.
-template <int N, int P, int ND, bool REGS, bool AW = false>
+template <int N, int P, int ND, bool REGS, bool AW = false, class LW = CdmLaw>
 __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P, ND, AW>& S,
                                        const MatP<typename Prec<P>::T>& m, int lane,
                                        typename Prec<P>::T* dreg) {
@@ -214,8 +214,8 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
       T u[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
-      cdm_tangent(u, m, law, ds);
-      r = -cdm_rate(u, m, law);   // negated: it joins the CK contraction stored with -1
+      LW::tangent(u, m, law, ds);
+      r = -LW::rate(u, m, law);   // negated: it joins the CK contraction stored with -1
       const T wq = (T)a.wq[q];
 #pragma unroll
       for (int k = 0; k < 6; ++k)
@@ -359,7 +359,7 @@ template <int N, int P> struct FwdRegs {
 // With one LDS derivative buffer the FP32 / BF16 forms fit 21 workgroups per
 // compute unit; asking for five wavefronts per SIMD keeps the registers within
 // that (96 per lane).  The FP64 form is held to ten workgroups by its LDS.
-template <int N, int P>
+template <int N, int P, class LW = CdmLaw>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FwdRegs<N, P>::value ? (P == PREC_F64 ? 2 : 5) : 1)))
 void k_predict_volume(StepArgs<P> a) {
   using PR = Prec<P>;
@@ -385,7 +385,7 @@ void k_predict_volume(StepArgs<P> a) {
   if (e >= a.E) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  predictor_stage<N, P, ND, REGS, true>(a, e, S, m, lane, dreg);
+  predictor_stage<N, P, ND, REGS, true, LW>(a, e, S, m, lane, dreg);
   // D^i[idx] for idx = lane + 64 j
   auto Dv = [&](int i, int j) -> T {
     if constexpr (REGS)
@@ -449,7 +449,7 @@ void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
         for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
         T sig[6];
-        sacc[c] += g * cdm_stress_rate(u, m, law, sig);
+        sacc[c] += g * LW::stress_rate(u, m, law, sig);
 #pragma unroll
         for (int k = 0; k < 6; ++k) ss[c][k] += g * sig[k];
 #pragma unroll
@@ -518,11 +518,12 @@ void k_predict_volume(StepArgs<P> a) {
   if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sW[lane * DS + 9];
 }
 
+
 // One wavefront per face (interior faces once, boundary faces once): traces of
 // both sides at the shared face points for every time point, LLF (or
 // boundary) flux with the normal of the face's first element, time quadrature.
 // Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
-template <int N, int P>
+template <int N, int P, class LW = CdmLaw>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 4 ? 1 : (P == PREC_F64 ? 4 : 7))))
 void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux) {
   using PR = Prec<P>;
@@ -585,9 +586,9 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
       const T* up = sTp + z * TS + i * R;
 #pragma unroll
       for (int k = 0; k < 10; ++k) uP[k] = up[k];
-      llf_flux(uM, uP, n, m, mp, law, F);
+      llf_flux<LW>(uM, uP, n, m, mp, law, F);
     } else {
-      boundary_flux(kind, uM, n, m, law, F);
+      boundary_flux<LW>(kind, uM, n, m, law, F);
     }
     const T g = a.gamma[z];
 #pragma unroll
@@ -603,6 +604,7 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
     out[idx] = s;
   }
 }
+
 
 // Face term and final update (Appendix A.2, Eq. time-integrated): each element
 // lifts the time-integrated flux of its four faces (negated where it is the
@@ -819,11 +821,15 @@ __global__ void k_reduce_sum(long long n, const double* in, double* out) {
 }
 
 __global__ void k_wavespeed(long long E, int L, const double* Ua, const double* mat, double amax,
-                            double phi0_mean, double* out) {
+                            double phi0_mean, int law, double* out) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   double ab = phi0_mean * Ua[e * L];
   ab = ab < 0.0 ? 0.0 : (ab > amax ? amax : ab);
+  if (law == 1) {   // shear modulus (1 - alpha) mu0 (Eq. effective-ivm)
+    out[e] = sqrt(1.0 - ab) - 1.0;
+    return;
+  }
   const double mu = mat[e * 8 + 2];
   double md = mu + ab * mat[e * 8 + 4] * mat[e * 8 + 3];
   md = md > 0.0 ? md : 0.0;

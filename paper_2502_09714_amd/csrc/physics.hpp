@@ -29,6 +29,11 @@ template <class T> struct Law {
   T smin;   // sqrt(I2) at or below which the xi and sqrt(I2) terms are dropped
 };
 
+// The rheology of a kernel instantiation: the continuum-damage law (Eq.
+// cdb-model) or the internal-variable law (Eq. ivm-model); both defined below.
+struct CdmLaw;
+struct IvmLaw;
+
 // Invariants computed from the strain scaled by its largest entry, so that the
 // scale-free quantities (xi and the tangent / acoustic-tensor directions) are
 // the same in FP32 and FP64 down to the guard sqrt(I2) <= smin.
@@ -131,11 +136,11 @@ __device__ __host__ constexpr int sym_idx(int i, int j) {
 }
 
 // F_n = n_d F^d(u) for the 10 quantities
-template <class T>
+template <class LW = CdmLaw, class T>
 __device__ inline void normal_flux(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law,
                                    T F[10]) {
   T sig[6];
-  cdm_stress(u, m, law, sig);
+  LW::stress(u, m, law, sig);
   const T* v = u + 6;
   F[0] = -v[0] * n[0];
   F[1] = -v[1] * n[1];
@@ -200,6 +205,110 @@ __device__ inline T llf_speed(const T* u, const T n[3], const MatP<T>& m, const 
   return lm > T(0) ? sqrt(lm) : T(0);
 }
 
+// Pointwise functions of the continuum-damage law
+struct CdmLaw {
+  template <class T>
+  __device__ static void stress(const T* u, const MatP<T>& m, const Law<T>& law, T sig[6]) {
+    cdm_stress(u, m, law, sig);
+  }
+  template <class T>
+  __device__ static T stress_rate(const T* u, const MatP<T>& m, const Law<T>& law, T sig[6]) {
+    return cdm_stress_rate(u, m, law, sig);
+  }
+  template <class T>
+  __device__ static T rate(const T* u, const MatP<T>& m, const Law<T>& law) {
+    return cdm_rate(u, m, law);
+  }
+  template <class T>
+  __device__ static void tangent(const T* u, const MatP<T>& m, const Law<T>& law, T ds[6][7]) {
+    cdm_tangent(u, m, law, ds);
+  }
+  template <class T>
+  __device__ static T speed(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law) {
+    return llf_speed(u, n, m, law);
+  }
+  // effective Lame parameters on boundaries (Eq. effective-cdb)
+  template <class T>
+  __device__ static void lame(const T* u, const MatP<T>& m, const Law<T>& law, T& lam, T& mu) {
+    Parts<T> p = cdm_parts(u, law);
+    lam = m.lam - p.ac * m.gr * p.xi / T(3);
+    mu = m.mu + p.ac * m.xi0 * m.gr - T(0.5) * p.ac * m.gr * p.xi;
+  }
+};
+
+// Internal-variable law with the Murnaghan terms off (Eq. ivm-model):
+//   sigma = (1 - alpha)(lambda0 I1 delta + 2 mu0 eps),
+//   r = [lambda0 I1^2 / 2 + mu0 I2 - gamma_b (alpha / (1 - alpha))^2] / (gamma_b tau_b),
+// alpha clamped to [0, amax].  Material slots: gr = gamma_b,
+// cd = 1 / (gamma_b tau_b) (xi0 unused).
+struct IvmLaw {
+  template <class T> struct Pt {
+    T I1, I2, g, ac, dac;
+  };
+  template <class T>
+  __device__ static Pt<T> parts(const T* u, const Law<T>& law) {
+    Pt<T> p;
+    p.I1 = u[0] + u[1] + u[2];
+    p.I2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] +
+           T(2) * (u[3] * u[3] + u[4] * u[4] + u[5] * u[5]);
+    const T a = u[9];
+    p.ac = a < T(0) ? T(0) : (a > law.amax ? law.amax : a);
+    p.dac = (a >= T(0) && a <= law.amax) ? T(1) : T(0);
+    p.g = T(1) - p.ac;
+    return p;
+  }
+  template <class T>
+  __device__ static void stress_p(const Pt<T>& p, const T* u, const MatP<T>& m, T sig[6]) {
+    const T c = T(2) * m.mu * p.g, iso = m.lam * p.g * p.I1;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sig[k] = c * u[k] + (k < 3 ? iso : T(0));
+  }
+  template <class T>
+  __device__ static T rate_p(const Pt<T>& p, const MatP<T>& m) {
+    const T q = p.ac / p.g;
+    return m.cd * (T(0.5) * m.lam * p.I1 * p.I1 + m.mu * p.I2 - m.gr * q * q);
+  }
+  template <class T>
+  __device__ static void stress(const T* u, const MatP<T>& m, const Law<T>& law, T sig[6]) {
+    stress_p(parts(u, law), u, m, sig);
+  }
+  template <class T>
+  __device__ static T stress_rate(const T* u, const MatP<T>& m, const Law<T>& law, T sig[6]) {
+    const Pt<T> p = parts(u, law);
+    stress_p(p, u, m, sig);
+    return rate_p(p, m);
+  }
+  template <class T>
+  __device__ static T rate(const T* u, const MatP<T>& m, const Law<T>& law) {
+    return rate_p(parts(u, law), m);
+  }
+  // d sigma_k / d u_q (q < 6 strain entries, q = 6 alpha)
+  template <class T>
+  __device__ static void tangent(const T* u, const MatP<T>& m, const Law<T>& law, T ds[6][7]) {
+    const Pt<T> p = parts(u, law);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        ds[k][q] = p.g * ((k == q ? T(2) * m.mu : T(0)) + (k < 3 && q < 3 ? m.lam : T(0)));
+      ds[k][6] = -p.dac * (T(2) * m.mu * u[k] + (k < 3 ? m.lam * p.I1 : T(0)));
+    }
+  }
+  // the acoustic tensor is that of the damaged isotropic moduli
+  template <class T>
+  __device__ static T speed(const T* u, const T n[3], const MatP<T>& m, const Law<T>& law) {
+    const Pt<T> p = parts(u, law);
+    return sqrt(p.g * (m.lam + T(2) * m.mu) / m.rho);
+  }
+  // effective Lame parameters on boundaries (Eq. effective-ivm)
+  template <class T>
+  __device__ static void lame(const T* u, const MatP<T>& m, const Law<T>& law, T& lam, T& mu) {
+    const Pt<T> p = parts(u, law);
+    lam = p.g * m.lam;
+    mu = p.g * m.mu;
+  }
+};
+
 template <class T>
 __device__ inline bool same_material(const MatP<T>& a, const MatP<T>& b) {
   return a.rho == b.rho && a.lam == b.lam && a.mu == b.mu && a.gr == b.gr && a.xi0 == b.xi0 &&
@@ -207,19 +316,19 @@ __device__ inline bool same_material(const MatP<T>& a, const MatP<T>& b) {
 }
 
 // Local Lax-Friedrichs flux at one face point
-template <class T>
+template <class LW = CdmLaw, class T>
 __device__ inline void llf_flux(const T* um, const T* up, const T n[3], const MatP<T>& mm,
                                 const MatP<T>& mp, const Law<T>& law, T F[10]) {
   T Fm[10], Fp[10], ub[10];
-  normal_flux(um, n, mm, law, Fm);
-  normal_flux(up, n, mp, law, Fp);
+  normal_flux<LW>(um, n, mm, law, Fm);
+  normal_flux<LW>(up, n, mp, law, Fp);
 #pragma unroll
   for (int k = 0; k < 10; ++k) ub[k] = T(0.5) * (um[k] + up[k]);
   // the speed at the mean state is the same for equal materials
-  const T c1 = llf_speed(ub, n, mm, law);
+  const T c1 = LW::speed(ub, n, mm, law);
   T C = c1;
   if (!same_material(mm, mp)) {
-    const T c2 = llf_speed(ub, n, mp, law);
+    const T c2 = LW::speed(ub, n, mp, law);
     C = c1 > c2 ? c1 : c2;
   }
 #pragma unroll
@@ -247,12 +356,11 @@ __device__ inline void face_frame(const T n[3], T s[3], T t[3]) {
 }
 
 // free surface (kind 1) or absorbing (kind 2) boundary flux from the interior trace
-template <class T>
+template <class LW = CdmLaw, class T>
 __device__ inline void boundary_flux(int kind, const T* u, const T n[3], const MatP<T>& m,
                                      const Law<T>& law, T F[10]) {
-  Parts<T> p = cdm_parts(u, law);
-  const T lam = m.lam - p.ac * m.gr * p.xi / T(3);
-  const T mu = m.mu + p.ac * m.xi0 * m.gr - T(0.5) * p.ac * m.gr * p.xi;
+  T lam, mu;
+  LW::lame(u, m, law, lam, mu);
   T s[3], t[3];
   face_frame(n, s, t);
   auto epsv = [&](const T* a, T out[3]) {
