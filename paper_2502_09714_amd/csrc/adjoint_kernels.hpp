@@ -6,10 +6,11 @@
 //   k_adj_face   one wavefront per face: traces of U_z and of lambda on both
 //                sides, cotangent of the single-valued flux from both sides'
 //                updates, flux VJP for both traces -> trace cotangents per face
+//   k_adj_lift   one wavefront per element: transposed lift of its four faces'
+//                trace cotangents -> face part of dJ/dU_z
 //   k_adj_volume one wavefront per element: predictor restored or recomputed;
 //                volume / source VJP at every (z, q); transposed nodal
-//                evaluation and transposed lift of the four faces' trace
-//                cotangents; Taylor and CK recursion reversed;
+//                evaluation; Taylor and CK recursion reversed;
 //                cell-averaged-tangent VJP (second derivatives of the stress);
 //                identity path -> lambda^n
 // Every wavefront writes only its own outputs (no atomics).

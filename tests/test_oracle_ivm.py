@@ -123,3 +123,21 @@ def test_inert_ivm_step_equals_undamaged_cdm_step():
     U[..., 9] = 0.0
     a, b = Si.step(U), Sc.step(U)
     assert float((a - b).abs().max()) <= 1e-12 * float(b[..., :9].abs().max())
+
+
+def test_ivm_workload_parameters():
+    """Table 2's storage-energy scales on the two kinds of unit, the shortened
+    time scale, the elastic model kept; an unknown rheology is refused."""
+    wc = make_workload("c2", n=3, N=1)
+    wi = make_workload("c2", n=3, N=1, rheology="ivm")
+    assert wi.rheology == "ivm" and wc.rheology == "cdm"
+    for k in ("rho", "lambda0", "mu0"):
+        assert np.array_equal(wi.material[k], wc.material[k])
+    cs = np.sqrt(wi.material["mu0"] / wi.material["rho"])
+    assert set(np.unique(wi.material["gamma_b"][cs < 1000.0])) == {0.5e3}
+    assert set(np.unique(wi.material["gamma_b"][cs >= 1000.0])) == {356e3}
+    assert np.all(wi.material["tau_b"] == 1e-4)
+    assert wi.dt == wc.dt
+    import pytest
+    with pytest.raises(ValueError):
+        make_workload("c2", n=3, N=1, rheology="plastic")
