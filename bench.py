@@ -82,10 +82,16 @@ def bytes_per_launch(w, prec):
 
 
 def kernel_source_hash():
+    """Hash of the step kernels' sources with comments and blank lines removed
+    (a comment edit does not change the measured code)."""
     h = hashlib.sha256()
     for f in ("kernels.hpp", "physics.hpp", "mfma.hpp"):
-        with open(os.path.join(ROOT, "paper_2502_09714_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2502_09714_amd", "csrc", f)) as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in src.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code.strip():
+                h.update((code + "\n").encode())
     return h.hexdigest()[:16]
 
 

@@ -17,6 +17,9 @@
 //   lambda_eff = lambda0 - a gamma_r xi / 3,  mu_eff = mu0 + a xi0 gamma_r - a gamma_r xi / 2
 // and the closed forms of T B^{1,eff} u^b (free surface: traction-free
 // Riemann state) and T R Lambda^+ R^{-1} T^{-1} u (absorbing).
+// The internal-variable law of Eq. ivm-model (IvmLaw below) replaces stress,
+// rate, tangent, Lax-Friedrichs speed and boundary moduli where a kernel is
+// instantiated with it; fluxes and boundary closed forms are shared.
 #pragma once
 #include <hip/hip_runtime.h>
 
