@@ -22,8 +22,10 @@ Module map
   refmat       reference matrices M, K^e, projection, traces, lift
   mesh         geometry, connectivity and neighbour point matching
   cdm          CDM stress, damage rate, flux, Jacobian, LLF constant
+  ivm          the same for the internal-variable law (Eq. ivm-model)
   boundary     free-surface and absorbing boundary fluxes
   step         predictor (linearised Cauchy-Kovalevskaya) + corrector
   sources      point moment-tensor sources and receivers
   diagnostics  energy and shear-wave-speed change
+  adjoint      gradients of a step and of a seismogram misfit (autograd)
 """
