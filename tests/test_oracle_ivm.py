@@ -9,7 +9,9 @@ the step with it.
   follows the ODE dalpha/dt = r_alpha to third order in dt per step (scipy's
   ODE solver gives the exact solution);
 * with a negligible damage rate and alpha = 0 the IVM step equals the CDM
-  step with no damage (the two laws share only the Hooke limit).
+  step with no damage (the two laws share only the Hooke limit);
+* the boundary fluxes at damage alpha equal the CDM ones of an undamaged
+  material with the damaged Lame parameters.
 """
 import math
 
@@ -141,3 +143,28 @@ def test_ivm_workload_parameters():
     import pytest
     with pytest.raises(ValueError):
         make_workload("c2", n=3, N=1, rheology="plastic")
+
+
+def test_ivm_boundary_fluxes_are_elastic_with_damaged_moduli():
+    """Free-surface and absorbing fluxes under the IVM law at damage alpha
+    equal those of an undamaged CDM material with Lame parameters
+    (1 - alpha) lambda0, (1 - alpha) mu0 (Eq. effective-ivm): two independent
+    routes to the effective moduli."""
+    from oracle import boundary
+    n = 30
+    g = torch.Generator().manual_seed(11)
+    u = torch.randn(n, 10, generator=g, dtype=DT) * 1e-4
+    u[:, 9] = 0.45 * torch.rand(n, generator=g, dtype=DT)
+    nrm = torch.randn(n, 3, generator=g, dtype=DT)
+    nrm = nrm / nrm.norm(dim=1, keepdim=True)
+    mi = _mat(n, 12)
+    gdam = 1.0 - u[:, 9]
+    mc = dict(rho=mi["rho"], lambda0=gdam * mi["lambda0"], mu0=gdam * mi["mu0"],
+              gamma_r=torch.zeros(n, dtype=DT), xi0=torch.full((n,), -0.75, dtype=DT),
+              Cd=torch.zeros(n, dtype=DT))
+    u0 = u.clone()
+    u0[:, 9] = 0.0
+    for fn in (boundary.free_surface_flux, boundary.absorbing_flux):
+        a = fn(u, nrm, mi, 0.5, lame=ivm.effective_lame)
+        b = fn(u0, nrm, mc, 0.5)
+        assert float((a[:, :9] - b[:, :9]).abs().max()) <= 1e-12 * float(b[:, :9].abs().max())
