@@ -2,15 +2,23 @@
 """Throughput of the CDM ADER-DG step on one MI355X.
 
 One step = one pass of the whole hot path (predictor, volume, faces,
-boundaries, update) over the synthetic workload.  Default workload: the
-mid-size configuration c2 -- 48^3 cubes x 6 = 663,552 tetrahedra, degree 3
-(20 modes, 200 DOFs per element), soft basin over rock, free top, absorbing
-sides, 32 Gaussian strain pulses, damage alpha0 ~ U(0, 0.05).  The FP32 form
-is the headline value; FP64 and BF16-MFMA forms run the same steps and are
-reported beside it with their L2 difference from the FP64 GPU state.
+boundaries, update, point sources, receivers) over the synthetic workload.
+Default workload: the largest configuration, c5 -- 96^3 cubes x 6 =
+5,308,416 tetrahedra, degree 4 (35 modes, 350 DOFs per element), 24 km box,
+3 km gradient basin over rock, free top, absorbing sides, 64 subfault point
+sources, 16 receivers.  The FP32 form is the headline value; the BF16-MFMA
+(split operands, FP32 accumulation) and FP64 forms run the same steps and
+are reported beside it with their device-memory footprint.
 
-Prints one JSON line (see the keys below).  The FP64 CPU oracle is timed on
-a bounded sample (the same recipe on a 6^3-cube mesh, 2 steps) on the host.
+Precision errors: the precision-form configuration c3 (64^3 cubes x 6 =
+1,572,864 tets, N = 4, lognormal moduli) is run in FP64, FP32 and BF16 from
+the same initial state for --error-steps steps (default 100; the specified
+1000 with --error-steps 1000), and the relative L2 and the pointwise maximum
+(at the volume quadrature points) of every quantity group are reported
+against the FP64 GPU state.
+
+Prints one JSON line.  The FP64 CPU oracle is timed on a bounded sample (the
+c5 recipe on a 3^3-cube mesh, a few steps, one thread and all threads).
 """
 import argparse
 import hashlib
@@ -27,9 +35,10 @@ if ROOT not in sys.path:
 METRIC = "DG DOF-updates/s on 1 GPU, FP32/BF16 vs FP64 at stated L2 error; adjoint/forward cost"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 HBM_TBS = 8.0
-KERNELS = ("predict_volume", "face_flux", "sources", "receivers",
-           "adj_predict_recompute", "adj_face", "adj_volume", "adj_receivers", "lift_update")
-STEP_KERNELS = ("predict_volume", "face_flux", "lift_update")
+KERNELS = ("predict", "face_flux", "sources", "receivers",
+           "adj_predict_recompute", "adj_face", "adj_volume", "adj_receivers", "lift_update",
+           "volume")
+STEP_KERNELS = ("predict", "volume", "face_flux", "lift_update")
 
 
 def dims(N):
@@ -52,17 +61,18 @@ def flops_per_launch(w):
     L, Q, Ns, Nt = dims(N)
     ne = w.ne
     ni, nb = face_counts(w)
-    k1_mm = (2 * Q * L * 10                       # nodal values at t_n
-             + N * (3 * L * 10 * 10 * 2 + 3 * L * L * 10 * 2)   # CK: U A*^T, K^e contraction
-             + 2 * L * Q                          # source projection at t_n
-             + Nt * (N + 1) * L * 10 * 2          # Taylor sums
-             + Nt * 2 * Q * L * 10                # nodal values at the time points
-             + 2 * 3 * L * Q * 9 + 2 * L * Q)     # volume and source contractions
-    k1_pw = Q * 400 + Nt * Q * 230
+    kp = (2 * Q * L * 10                          # nodal values at t_n
+          + N * (3 * L * 10 * 10 * 2 + 3 * L * L * 10 * 2)   # CK: U A*^T, K^e contraction
+          + 2 * L * Q                             # source projection at t_n
+          + Nt * (N + 1) * L * 10 * 2             # Taylor sums
+          + Q * 400)                              # pointwise tangent at t_n
+    kv = (Nt * 2 * Q * L * 10                     # nodal values at the time points
+          + 2 * 3 * L * Q * 9 + 2 * L * Q         # volume and source contractions
+          + Nt * Q * 230)                         # stress, flux, damage rate per (z, q)
     trace = Nt * 2 * Ns * L * 10                  # one side's traces at all time points
     ff = ni * (2 * trace + Ns * Nt * 470 + Ns * Nt * 10 * 2) + nb * (trace + Ns * Nt * 300 + Ns * Nt * 10 * 2)
     lift = ne * (4 * 2 * L * Ns * 10 + 4 * Ns * 10 + 10 * L)
-    return {"predict_volume": (k1_mm + k1_pw) * ne, "face_flux": ff, "lift_update": lift}
+    return {"predict": kp * ne, "volume": kv * ne, "face_flux": ff, "lift_update": lift}
 
 
 def bytes_per_launch(w, prec):
@@ -74,24 +84,33 @@ def bytes_per_launch(w, prec):
     t = 8 if prec == "fp64" else 4
     state = 9 * L * t + L * 8
     uz = Nt * 10 * L * t
-    k1 = ne * (state + uz + state + 16 * 8 + 8 * 8)     # read U, write U_z, write partial
+    kp = ne * (state + uz + 16 * 8 + 8 * 8)             # read U, write U_z
+    kv = ne * (uz + 2 * state + 16 * 8 + 8 * 8)         # read U_z and U, write the partial update
     flux = Ns * 10 * t
     ff = ne * uz + (ni + nb) * (flux + 8 * 4) + ne * (4 * 4 * 8 + 8 * 8)
     k3 = ne * (4 * flux + 2 * state + 4 * 4 * 8 + 4 * 4)
-    return {"predict_volume": k1, "face_flux": ff, "lift_update": k3}
+    return {"predict": kp, "volume": kv, "face_flux": ff, "lift_update": k3}
+
+
+HASHED_SOURCES = ("kernels.hpp", "physics.hpp", "mfma.hpp", "dgd.hip")
 
 
 def kernel_source_hash():
-    """Hash of the step kernels' sources with comments and blank lines removed
-    (a comment edit does not change the measured code)."""
+    """Hash of the device sources (kernels, their launch code in dgd.hip) with
+    comments and blank lines removed (a comment edit does not change the
+    measured code), and of the compiler flags of the build."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "physics.hpp", "mfma.hpp"):
+    for f in HASHED_SOURCES:
         with open(os.path.join(ROOT, "paper_2502_09714_amd", "csrc", f)) as fh:
             src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in src.splitlines():
             code = line.split("//", 1)[0].rstrip()
             if code.strip():
                 h.update((code + "\n").encode())
+    with open(os.path.join(ROOT, "paper_2502_09714_amd", "build.py")) as fh:
+        m = re.search(r"HIPCC_FLAGS = \[(.*?)\]", fh.read(), flags=re.S)
+    flags = re.findall(r'"([^"]+)"', m.group(1)) if m else []
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 
@@ -112,7 +131,11 @@ def load_traffic(kernel, workload, prec):
 def run_precision(w, prec, steps, warmup, want_state=True):
     import torch
     from paper_2502_09714_amd.api import from_workload
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     sim = from_workload(w, prec)
+    sim.synchronize()
+    footprint = free0 - torch.cuda.mem_get_info()[0]
     sim.set_check_interval(1 << 40)
     sim.step(warmup)
     sim.synchronize()
@@ -128,6 +151,7 @@ def run_precision(w, prec, steps, warmup, want_state=True):
     sim.set_profiling(False)
     state = sim.get_state() if want_state else None
     out = {"seconds": t1 - t0, "ms_per_step": 1e3 * (t1 - t0) / steps,
+           "device_bytes": int(footprint),
            "kernel_ms": {k: float(ms[i]) for i, k in enumerate(KERNELS)},
            "kernel_launches": {k: int(launches[i]) for i, k in enumerate(KERNELS)},
            "state": state, "L": sim.L, "ne": sim.ne}
@@ -199,31 +223,124 @@ def rel_l2(a, b):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(name, n_sample, steps):
+    """The FP64 oracle on the host's cores: the same recipe on a small cut
+    (n_sample^3 cubes), `steps` steps with one thread and with all the threads
+    torch uses here (the host's share of cores), after one untimed step."""
     import torch
     from oracle.step import from_workload as oracle_from
     from workloads import make_workload
-    threads = min(16, os.cpu_count() or 1)
-    torch.set_num_threads(threads)
+    nproc = os.cpu_count() or 1
+    allt = torch.get_num_threads()
     w = make_workload(name, n=n_sample)
     S = oracle_from(w)
     U = S.project(w.ic)
     U = S.step(U)                      # first call pays one-time set-up costs
-    t0 = time.perf_counter()
-    S.run(U, steps)
-    dt = time.perf_counter() - t0
     dofs = w.ne * w.L * 10
-    return {"value": dofs * steps / dt, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{name} recipe on {n_sample}^3 cubes x 6 = {w.ne} tets, N={w.N}, "
-                      f"{steps} steps after one untimed step, {dt:.1f} s, torch float64 CPU"}
+    rates, secs = {}, {}
+    for th in (allt, 1):
+        torch.set_num_threads(th)
+        t0 = time.perf_counter()
+        S.run(U, steps)
+        secs[th] = time.perf_counter() - t0
+        rates[th] = dofs * steps / secs[th]
+    torch.set_num_threads(allt)
+    return {"value": rates[allt], "unit": "DOF-updates/s", "cores": allt, "kind": "oracle",
+            "one_thread_value": rates[1], "nproc": nproc, "cpu_model": cpu_model(),
+            "sample": f"{name} recipe cut to {n_sample}^3 cubes x 6 = {w.ne} tets, N={w.N}: "
+                      f"{steps} steps after one untimed step, {secs[allt]:.1f} s on {allt} threads "
+                      f"and {secs[1]:.1f} s on 1 thread, torch float64 CPU; the rate is per "
+                      f"DOF-update and carries over to the full mesh (the oracle is linear in "
+                      f"the element count), i.e. extrapolated, not run at full size"}
+
+
+GROUPS = (("strain", 0, 6), ("velocity", 6, 9), ("alpha", 9, 10))
+
+
+def precision_errors(name, steps, precs, chunk=1 << 14):
+    """Relative L2 (modal, uniform mesh) and pointwise maximum error (at the
+    volume quadrature points, relative to the largest FP64 value) per quantity
+    group of each precision against the FP64 GPU run, after `steps` steps from
+    the same initial state (the FP64 projection of the initial condition)."""
+    import torch
+    from paper_2502_09714_amd.api import from_workload
+    from workloads import make_workload
+    w = make_workload(name)
+    w.sources = None
+    w.receivers = None
+    ref = from_workload(w, "fp64")
+    U0 = torch.empty((ref.ne, 10, ref.L), dtype=torch.float64, device="cuda")
+    ref.get_state(U0)
+    sims = {}
+    for p in precs:
+        sims[p] = from_workload(w, p, state=False)
+        sims[p].set_state(U0)
+    del U0
+    t = {}
+    for p, sim in [("fp64", ref)] + list(sims.items()):
+        sim.set_check_interval(1 << 40)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        t[p] = time.perf_counter() - t0
+        print(f"errors {name}: {p} {steps} steps in {t[p]:.1f} s", file=sys.stderr, flush=True)
+    Q, L = ref.Q, ref.L
+    acc = {p: {g: [0.0, 0.0] for g, _, _ in GROUPS} for p in precs}   # sum d^2, max |d|
+    ref_acc = {g: [0.0, 0.0] for g, _, _ in GROUPS}
+    for e0 in range(0, ref.ne, chunk):
+        cnt = min(chunk, ref.ne - e0)
+        pr = torch.empty((cnt, Q, 10), dtype=torch.float64, device="cuda")
+        ref.get_point_values(e0, cnt, pr)
+        mr = torch.empty((cnt * 10 * L,), dtype=torch.float64, device="cuda")
+        for p, sim in sims.items():
+            pp = torch.empty_like(pr)
+            sim.get_point_values(e0, cnt, pp)
+            for g, a, b in GROUPS:
+                acc[p][g][1] = max(acc[p][g][1], float((pp[..., a:b] - pr[..., a:b]).abs().max()))
+        for g, a, b in GROUPS:
+            ref_acc[g][1] = max(ref_acc[g][1], float(pr[..., a:b].abs().max()))
+        del pr, mr
+    Ur = torch.empty((ref.ne, 10, L), dtype=torch.float64, device="cuda")
+    ref.get_state(Ur)
+    for g, a, b in GROUPS:
+        ref_acc[g][0] = float((Ur[:, a:b] ** 2).sum())
+    for p, sim in sims.items():
+        Up = torch.empty_like(Ur)
+        sim.get_state(Up)
+        for g, a, b in GROUPS:
+            acc[p][g][0] = float(((Up[:, a:b] - Ur[:, a:b]) ** 2).sum())
+        del Up
+        sim.close()
+    ref.close()
+    out = {"workload": f"{name}: {w.mesh['n']}^3 cubes x 6 = {w.ne} tets, N={w.N}, "
+                       f"{steps} steps from the same state (no sources)",
+           "steps": steps, "reference": "fp64 GPU",
+           "seconds": {p: round(v, 2) for p, v in t.items()}}
+    for p in precs:
+        out[p] = {g: {"l2": (acc[p][g][0] / ref_acc[g][0]) ** 0.5 if ref_acc[g][0] > 0 else 0.0,
+                      "linf": acc[p][g][1] / ref_acc[g][1] if ref_acc[g][1] > 0 else 0.0}
+                  for g, _, _ in GROUPS}
+    return out
 
 
 def run_ivm(args, precs, dofs):
     """Step timing of the benchmark workload with the IVM law, per precision."""
     from workloads import make_workload
     wi = make_workload(args.workload, n=args.n, rheology="ivm")
-    ri = {p: run_precision(wi, p, args.steps, args.warmup) for p in precs}
+    ri = {p: run_precision(wi, p, args.steps, args.warmup, want_state="fp64" in precs)
+          for p in precs}
     iv = {"workload": f"{args.workload} with the IVM law", "steps": args.steps}
     for p in precs:
         iv[f"{p}_ms_per_step"] = ri[p]["ms_per_step"]
@@ -240,21 +357,26 @@ def run_ivm(args, precs, dofs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--n", type=int, default=None, help="override the cube count")
-    ap.add_argument("--precisions", default="fp32,fp64,bf16")
+    ap.add_argument("--precisions", default="fp32,bf16,fp64")
+    ap.add_argument("--error-workload", default="c3",
+                    help="workload of the precision-error table ('' for none)")
+    ap.add_argument("--error-steps", type=int, default=100)
+    ap.add_argument("--error-precisions", default="fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=6)
-    ap.add_argument("--cpu-steps", type=int, default=4)
-    ap.add_argument("--adjoint-precisions", default="fp32,fp64",
-                    help="precisions whose checkpointed adjoint is timed ('' for none)")
+    ap.add_argument("--cpu-sample-n", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--adjoint-precisions", default="",
+                    help="precisions whose checkpointed adjoint is timed on the step workload "
+                         "('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
     ap.add_argument("--adjoint-workload", default="c4",
                     help="workload of the full-length adjoint timing ('' for none)")
     ap.add_argument("--adjoint-workload-precisions", default="fp32")
-    ap.add_argument("--ivm-precisions", default="fp32,fp64",
+    ap.add_argument("--ivm-precisions", default="fp32",
                     help="precisions of the IVM-rheology step timing ('' for none)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
@@ -281,7 +403,8 @@ def main():
     main_prec = precs[0]
     res = {}
     for p in precs:
-        res[p] = run_precision(w, p, args.steps, args.warmup)
+        # the precision errors come from the c3 table below, not from these states
+        res[p] = run_precision(w, p, args.steps, args.warmup, want_state=False)
         print(f"{p}: {res[p]['ms_per_step']:.3f} ms/step  kernels {res[p]['kernel_ms']}",
               file=sys.stderr, flush=True)
     L = res[main_prec]["L"]
@@ -317,18 +440,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w.mesh['n']}^3 cubes x 6 = {ne} tets, N={w.N} "
                                f"({L} modes, {L * 10} DOFs/element), {main_prec} with FP64 alpha",
-                   "tets": ne, "degree": w.N, "dofs": dofs, "dt": w.dt},
+                   "tets": ne, "degree": w.N, "dofs": dofs, "dt": w.dt,
+                   "point_sources": 0 if w.sources is None else len(w.sources["xyz"]),
+                   "receivers": 0 if w.receivers is None else len(w.receivers)},
         "roofline": roof,
         "kernels": other,
     }
     for p in precs:
         line[f"{p}_dof_updates_per_s"] = rate(p)
         line[f"{p}_ms_per_step"] = res[p]["ms_per_step"]
+        line[f"{p}_device_bytes"] = res[p]["device_bytes"]
+        line[f"{p}_kernel_ms_per_step"] = {k: res[p]["kernel_ms"][k] / args.steps for k in STEP_KERNELS}
     if "fp64" in res:
         for p in precs:
             if p != "fp64":
                 line[f"speedup_{p}_vs_fp64"] = rate(p) / rate("fp64")
-                line[f"l2_{p}_vs_fp64_gpu"] = rel_l2(res[p]["state"], res["fp64"]["state"])
     ivm_precs = [q.strip() for q in args.ivm_precisions.split(",") if q.strip()]
     if ivm_precs:
         # the same workload with the internal-variable rheology (Eq. ivm-model);
@@ -350,6 +476,10 @@ def main():
             a = run_adjoint(wa, p, wa.nsteps, 20, observed=True)
             print(f"adjoint {args.adjoint_workload} {p}: {a}", file=sys.stderr, flush=True)
             line[f"adjoint_{args.adjoint_workload}_{p}"] = a
+    if args.error_workload:
+        eprecs = [q.strip() for q in args.error_precisions.split(",") if q.strip()]
+        line["precision_errors"] = precision_errors(args.error_workload, args.error_steps, eprecs)
+        print(f"precision errors: {line['precision_errors']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n, args.cpu_steps)
     print(json.dumps(line), flush=True)

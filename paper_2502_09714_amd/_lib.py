@@ -36,6 +36,8 @@ _SIGS = {
     "dgd_set_state_from_points": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, c_dp]),
     "dgd_set_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int]),
     "dgd_get_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int]),
+    "dgd_get_point_values": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_int]),
     "dgd_set_time": (ctypes.c_int, [H, ctypes.c_double]),
     "dgd_get_time": (ctypes.c_int, [H, c_dp]),
     "dgd_set_point_sources": (ctypes.c_int, [H, ctypes.c_int, c_dp, c_dp, c_dp, c_dp, ctypes.c_int]),
@@ -51,12 +53,15 @@ _SIGS = {
     "dgd_get_time_point_states": (ctypes.c_int, [H, c_dp]),
     "dgd_set_profiling": (ctypes.c_int, [H, ctypes.c_int]),
     "dgd_get_kernel_times": (ctypes.c_int, [H, c_dp, c_i64p]),
-    "dgd_adjoint_step": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
+    "dgd_adjoint_step": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "dgd_adjoint_step_host": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
     "dgd_forward_checkpointed": (ctypes.c_int, [H, ctypes.c_int64, ctypes.c_int64]),
     "dgd_backward": (ctypes.c_int, [H, c_dp, c_dp, c_dp, c_dp]),
+    "dgd_tape_id": (ctypes.c_int, [H, c_i64p]),
     "dgd_release_tape": (ctypes.c_int, [H]),
 }
-NUM_KERNEL_CLASSES = 9
+NUM_KERNEL_CLASSES = 10
 
 
 def lib():

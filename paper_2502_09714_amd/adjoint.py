@@ -29,10 +29,14 @@ class _Seismograms(torch.autograd.Function):
         sim.clear_seismograms()
         sim.forward_checkpointed(nsteps, every)
         ctx.sim = sim
+        ctx.tape = sim.tape_id()
         return torch.as_tensor(sim.get_seismograms(), dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, g):
+        if ctx.sim.tape_id() != ctx.tape:
+            raise RuntimeError("the solver no longer holds the checkpointed run of this graph "
+                               "(another forward run or a change of the problem since)")
         gmu, gcd = ctx.sim.backward(g.detach().cpu().numpy())
         return (torch.as_tensor(gmu), torch.as_tensor(gcd), None, None, None, None, None)
 

@@ -117,6 +117,22 @@ class Simulation:
             self._chk(self._L.dgd_get_state(self.h, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
+    def get_point_values(self, e0=0, count=None, out=None):
+        """Point values (count, Q, 10) at the volume quadrature points, FP64;
+        out: None (a new numpy array) or a float64 device tensor."""
+        count = self.ne - e0 if count is None else count
+        if out is None:
+            out = np.zeros((count, self.Q, 10))
+        if isinstance(out, np.ndarray):
+            assert out.dtype == np.float64 and out.size == count * self.Q * 10
+            self._chk(self._L.dgd_get_point_values(self.h, int(e0), int(count),
+                                                   out.ctypes.data_as(ctypes.c_void_p), 0))
+        else:
+            assert out.is_cuda and out.is_contiguous() and out.numel() == count * self.Q * 10
+            self._chk(self._L.dgd_get_point_values(self.h, int(e0), int(count),
+                                                   ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
     def set_time(self, t):
         self._chk(self._L.dgd_set_time(self.h, float(t)))
 
@@ -174,23 +190,46 @@ class Simulation:
         self._chk(self._L.dgd_set_profiling(self.h, int(bool(on))))
 
     def get_kernel_times(self):
-        """(ms[9], launches[9]) for predictor+volume, face fluxes, sources,
+        """(ms[10], launches[10]) for the predictor, face fluxes, sources,
         receivers, the adjoint's predictor recomputation, faces, volume,
-        receivers, and the lift + update."""
+        receivers, the lift + update, and the volume integrals."""
         ms = np.zeros(NUM_KERNEL_CLASSES)
         n = np.zeros(NUM_KERNEL_CLASSES, dtype=np.int64)
         self._chk(self._L.dgd_get_kernel_times(self.h, _dp(ms), n.ctypes.data_as(c_i64p)))
         return ms, n
 
     # ---- discrete adjoint ----------------------------------------------------------
-    def adjoint_step(self, lam_next):
-        """(lam_n, grad_mu0, grad_cd) of one step at the current state."""
+    def adjoint_step(self, state_n, lam, dl_dseis=None, grad_mu0=None, grad_cd=None):
+        """One reverse step on the device (dgd_adjoint_step): float64 torch
+        tensors on the device, state_n and lam (ne, 10, L), dl_dseis (nrec, 3)
+        or None, grad_mu0 / grad_cd (ne,) or None.  lam is overwritten with
+        lambda^n; the step's gradients are added to grad_mu0, grad_cd."""
+        def ptr(t, n):
+            if t is None:
+                return None
+            assert t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
+            assert t.is_contiguous() and t.numel() == n
+            return ctypes.c_void_p(t.data_ptr())
+        n = self.ne * 10 * self.L
+        self._chk(self._L.dgd_adjoint_step(self.h, ptr(state_n, n), ptr(lam, n),
+                                           ptr(dl_dseis, self.nrec * 3),
+                                           ptr(grad_mu0, self.ne), ptr(grad_cd, self.ne)))
+
+    def adjoint_step_host(self, lam_next):
+        """(lam_n, grad_mu0, grad_cd) of one step at the current state, host
+        arrays (dgd_adjoint_step_host, a test helper)."""
         lam = _f64(lam_next, (self.ne, 10, self.L))
         out = np.zeros((self.ne, 10, self.L))
         gmu = np.zeros(self.ne)
         gcd = np.zeros(self.ne)
-        self._chk(self._L.dgd_adjoint_step(self.h, _dp(lam), _dp(out), _dp(gmu), _dp(gcd)))
+        self._chk(self._L.dgd_adjoint_step_host(self.h, _dp(lam), _dp(out), _dp(gmu), _dp(gcd)))
         return out, gmu, gcd
+
+    def tape_id(self):
+        """Id of the kept checkpointed run (0: none)."""
+        i = ctypes.c_int64()
+        self._chk(self._L.dgd_tape_id(self.h, ctypes.byref(i)))
+        return i.value
 
     def forward_checkpointed(self, nsteps, every):
         self._chk(self._L.dgd_forward_checkpointed(self.h, int(nsteps), int(every)))

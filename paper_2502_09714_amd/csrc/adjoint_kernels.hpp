@@ -1,8 +1,8 @@
 // Discrete adjoint of one ADER-DG step (device), transposing every stage of
-// k_predict_volume / k_face_flux / k_lift_update:  given U^n and lambda^{n+1} = dJ/dU^{n+1}
+// k_predict + k_volume / k_face_flux / k_lift_update:  given U^n and lambda^{n+1} = dJ/dU^{n+1}
 // it returns lambda^n = dJ/dU^n and accumulates dJ/dmu0, dJ/dC_d per element.
 //
-//   k_predict_volume (forward, recomputed)  ->  time-point states U_z of all elements
+//   k_predict (forward, recomputed)         ->  time-point states U_z of all elements
 //   k_adj_face   one wavefront per face: traces of U_z and of lambda on both
 //                sides, cotangent of the single-valued flux from both sides'
 //                updates, flux VJP for both traces -> trace cotangents per face

@@ -17,12 +17,12 @@ using namespace dgd;
 
 namespace {
 
-struct Bf16x4 { uint16_t v[4]; };
+struct Bf16x8 { uint16_t v[8]; };   // high parts of four values, then their low parts
 
 template <int P> struct HostAF;
 template <> struct HostAF<PREC_F64> { using type = double; };
 template <> struct HostAF<PREC_F32> { using type = float; };
-template <> struct HostAF<PREC_BF16> { using type = Bf16x4; };
+template <> struct HostAF<PREC_BF16> { using type = Bf16x8; };
 
 struct DevBuf {
   void* p = nullptr;
@@ -56,7 +56,7 @@ struct dgd_handle {
   std::vector<double> rho_h;
   int law = 0;   // 0: continuum damage (Eq. cdb-model), 1: internal variable (Eq. ivm-model)
   // state
-  DevBuf U9[2], Ua[2], Uz, flag, scratch;
+  DevBuf U9[2], Ua[2], Uz, flag, tmp;   // tmp: per-call host transfers
   int cur = 0;
   double dt = 0.0, amax = 0.5, t = 0.0;
   long long steps_since_check = 0, check_every = 64;
@@ -70,6 +70,7 @@ struct dgd_handle {
   // discrete adjoint: transposed reference data, adjoint state, checkpoints
   DevBuf VTpk, STpk, PTpk, KTpk;
   DevBuf lam[2], gtr, gmuf, lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, segd, segacc, save9, savea;
+  DevBuf st9, sta;               // the state U^n handed to dgd_adjoint_step, working precision
   void* uz_override = nullptr;   // time-point states of the step being replayed
   void* d_keep = nullptr;        // where that replay keeps D^1..D^N (or null)
   void* acc_keep = nullptr;      // where it keeps the cell-averaged tangents (or null)
@@ -77,16 +78,18 @@ struct dgd_handle {
   std::vector<double> ck_t;
   long long tape_steps = 0, tape_every = 0, tape_seis0 = 0;
   bool tape = false;
+  long long tape_id = 0, tapes_made = 0;   // id of the kept tape (0: none)
+  std::vector<double> mat_h;               // host copy of the material table [E][8]
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 
   ~dgd_handle() {
     DevBuf* all[] = {&Vpk, &Kpk, &Spk, &Fpk, &Lpk, &Ppk, &Vd, &wqd, &Pwd, &betad, &geo, &fgeo,
-                     &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &scratch,
+                     &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &tmp,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &gtr, &gmuf, &lzf, &gmu, &gcd, &adjW9,
-                     &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea};
+                     &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea, &st9, &sta};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
@@ -142,6 +145,12 @@ dgd_status upload(dgd_handle* h, DevBuf& b, const std::vector<V>& v) {
 
 uint16_t bf16_bits(double x) { return f32_to_bf16((float)x); }
 
+float bf16_value(uint16_t b) {
+  union { uint32_t u; float f; } v;
+  v.u = (uint32_t)b << 16;
+  return v.f;
+}
+
 // pack A (rows x cols via accessor) into fragment order [tile][kstep][lane]
 template <int P, class F>
 std::vector<typename HostAF<P>::type> pack_A(F A, int tiles, int ksteps) {
@@ -154,7 +163,12 @@ std::vector<typename HostAF<P>::type> pack_A(F A, int tiles, int ksteps) {
         const int m = 16 * t + (lane & 15);
         AF& o = out[((size_t)t * ksteps + s) * 64 + lane];
         if constexpr (P == PREC_BF16) {
-          for (int j = 0; j < 4; ++j) o.v[j] = bf16_bits(A(m, KS * s + 4 * (lane >> 4) + j));
+          // split of the FP32 value into high and low BF16 parts
+          for (int j = 0; j < 4; ++j) {
+            const float x = (float)A(m, KS * s + 4 * (lane >> 4) + j);
+            o.v[j] = bf16_bits(x);
+            o.v[4 + j] = bf16_bits(x - bf16_value(o.v[j]));
+          }
         } else {
           o = (AF)A(m, KS * s + (lane >> 4));
         }
@@ -339,9 +353,15 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
     StepArgs<P> a = make_args<N, P>(h);
     timed(h, 0, [&] {
       if (ivm)
-        hipLaunchKernelGGL((k_predict_volume<N, P, IvmLaw>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((k_predict<N, P, IvmLaw>), grid, block, 0, h->stream, a);
       else
-        hipLaunchKernelGGL((k_predict_volume<N, P, CdmLaw>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((k_predict<N, P, CdmLaw>), grid, block, 0, h->stream, a);
+    });
+    timed(h, 9, [&] {
+      if (ivm)
+        hipLaunchKernelGGL((k_volume<N, P, IvmLaw>), grid, block, 0, h->stream, a);
+      else
+        hipLaunchKernelGGL((k_volume<N, P, CdmLaw>), grid, block, 0, h->stream, a);
     });
     const long long fper = (h->nfaces + 7) / 8;
     timed(h, 1, [&] {
@@ -417,7 +437,7 @@ template <int N, int P> struct PredictFn {
   static dgd_status run(dgd_handle* h) {
     const long long per = (h->ne + 7) / 8;
     StepArgs<P> a = make_args<N, P>(h);
-    hipLaunchKernelGGL((k_predict_volume<N, P>), dim3((unsigned)(8 * per)), dim3(64), 0, h->stream, a);
+    hipLaunchKernelGGL((k_predict<N, P>), dim3((unsigned)(8 * per)), dim3(64), 0, h->stream, a);
     HIPCHK(h, hipGetLastError());
     return DGD_OK;
   }
@@ -447,7 +467,8 @@ dgd_status alloc_adjoint(dgd_handle* h) {
 // material cotangents of this step to gmu, gcd
 template <int N, int P>
 dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, const void* lam_in,
-                             void* lam_out, void* uz, const void* dk, const void* ak) {
+                             void* lam_out, void* uz, const void* dk, const void* ak, double* gmu,
+                             double* gcd) {
   using T = typename Prec<P>::T;
   using AF = typename Prec<P>::AF;
   if constexpr (P == PREC_BF16) {
@@ -477,11 +498,11 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
     A.beta = (const double*)h->betad.p;
     A.Dkept = (const T*)dk;
     A.Akept = (const T*)ak;
-    A.gmu = (double*)h->gmu.p;
-    A.gcd = (double*)h->gcd.p;
+    A.gmu = gmu ? gmu : (double*)h->gmu.p;
+    A.gcd = gcd ? gcd : (double*)h->gcd.p;
     // time-point states of this step: recomputed unless the replay kept them
     if (!uz)
-      timed(h, 4, [&] { hipLaunchKernelGGL((k_predict_volume<N, P>), grid, block, 0, h->stream, a); });
+      timed(h, 4, [&] { hipLaunchKernelGGL((k_predict<N, P>), grid, block, 0, h->stream, a); });
     const long long fper = (h->nfaces + 7) / 8;
     timed(h, 5, [&] {
       hipLaunchKernelGGL((k_adj_face<N, P>), dim3((unsigned)(8 * fper)), block, 0, h->stream, A,
@@ -496,8 +517,8 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
 
 template <int N, int P> struct AdjStepFn {
   static dgd_status run(dgd_handle* h, const void* U9, const double* Ua, const void* li, void* lo,
-                        void* uz, const void* dk, const void* ak) {
-    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo, uz, dk, ak);
+                        void* uz, const void* dk, const void* ak, double* gmu, double* gcd) {
+    return adjoint_step_impl<N, P>(h, U9, Ua, li, lo, uz, dk, ak, gmu, gcd);
   }
 };
 
@@ -522,11 +543,54 @@ void release_tape(dgd_handle* h) {
   h->cka.clear();
   h->ck_t.clear();
   h->tape = false;
+  h->tape_id = 0;
   h->tape_steps = h->tape_every = 0;
+}
+
+// Every change of the problem definition (mesh, material, law, dt, alpha_max,
+// sources, receivers) drops the checkpointed run: its replay would use the new
+// definition and its buffers may not match the new mesh.
+void invalidate_tape(dgd_handle* h) {
+  if (h->tape) (void)hipStreamSynchronize(h->stream);
+  release_tape(h);
+}
+
+// The clamp alpha_max must keep the boundary moduli positive for every state:
+// CDM (Eq. effective-cdb with reading R4) mu_eff = mu0 + a xi0 gamma_r -
+// a gamma_r xi / 2 and lambda_eff + 2 mu_eff = lambda0 + 2 mu0 + 2 a xi0
+// gamma_r - 4 a gamma_r xi / 3 are linear in a in [0, alpha_max] and in
+// xi = I1/sqrt(I2) in [-sqrt 3, sqrt 3] (Cauchy-Schwarz), so their minima sit
+// at the corners; IVM (Eq. ivm-model) needs alpha_max < 1 (the storage energy
+// is singular at alpha = 1).
+bool moduli_admissible(int law, double amax, const std::vector<double>& m, long long ne,
+                       std::string* why) {
+  if (law == 1) {
+    if (!(amax < 1.0)) {
+      *why = "alpha_max must be below 1 under the internal-variable law";
+      return false;
+    }
+    return true;
+  }
+  const double r3 = std::sqrt(3.0);
+  for (long long e = 0; e < ne; ++e) {
+    const double lam = m[e * 8 + 1], mu = m[e * 8 + 2], gr = m[e * 8 + 3], xi0 = m[e * 8 + 4];
+    for (double a : {0.0, amax})
+      for (double xi : {-r3, r3}) {
+        const double mue = mu + a * xi0 * gr - 0.5 * a * gr * xi;
+        const double pm = lam + 2.0 * mu + 2.0 * a * xi0 * gr - 4.0 / 3.0 * a * gr * xi;
+        if (!(mue > 0.0) || !(pm > 0.0)) {
+          *why = "alpha_max " + std::to_string(amax) + " makes the effective moduli of element " +
+                 std::to_string(e) + " non-positive";
+          return false;
+        }
+      }
+  }
+  return true;
 }
 
 dgd_status copy_state(dgd_handle* h, void* d9, void* da, const void* s9, const void* sa) {
   const size_t E = (size_t)h->ne, L = h->ref.L;
+  if (!d9 || !da || !s9 || !sa) return fail(h, DGD_ESTATE, "state copy between missing buffers");
   HIPCHK(h, hipMemcpyAsync(d9, s9, E * 9 * L * h->tsize, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(da, sa, E * L * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   return DGD_OK;
@@ -706,6 +770,7 @@ dgd_status dgd_set_mesh(dgd_handle* h, int64_t nv, const double* xyz, int64_t ne
   if (!h) return DGD_EINVAL;
   if (nv <= 0 || ne <= 0 || !xyz || !tets || !face_tag) return fail(h, DGD_EINVAL, "bad mesh arguments");
   if (ne > (1LL << 30)) return fail(h, DGD_EINVAL, "too many elements");
+  invalidate_tape(h);
   h->have_mesh = h->have_state = false;
   std::vector<long long> ids((size_t)ne * 4);
   for (long long i = 0; i < ne * 4; ++i) {
@@ -843,7 +908,6 @@ dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lamb
   if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
   if (!rho || !lambda0 || !mu0 || !gamma_r || !xi0 || !Cd) return fail(h, DGD_EINVAL, "null array");
   std::vector<double> m((size_t)h->ne * 8, 0.0);
-  h->rho_h.assign(rho, rho + h->ne);
   for (long long e = 0; e < h->ne; ++e) {
     if (!(rho[e] > 0.0) || !(mu0[e] > 0.0)) return fail(h, DGD_EINVAL, "rho and mu0 must be positive");
     m[e * 8 + 0] = rho[e];
@@ -853,8 +917,14 @@ dgd_status dgd_set_material(dgd_handle* h, const double* rho, const double* lamb
     m[e * 8 + 4] = xi0[e];
     m[e * 8 + 5] = Cd[e];
   }
+  std::string why;
+  if (h->have_params && !moduli_admissible(0, h->amax, m, h->ne, &why))
+    return fail(h, DGD_EINVAL, why);
+  invalidate_tape(h);
   dgd_status s = upload(h, h->mat, m);
   if (s) return s;
+  h->rho_h.assign(rho, rho + h->ne);
+  h->mat_h.swap(m);
   h->law = 0;
   h->have_mat = true;
   return DGD_OK;
@@ -876,9 +946,14 @@ dgd_status dgd_set_material_ivm(dgd_handle* h, const double* rho, const double* 
     m[e * 8 + 3] = gamma_b[e];
     m[e * 8 + 5] = 1.0 / (gamma_b[e] * tau_b[e]);
   }
+  std::string why;
+  if (h->have_params && !moduli_admissible(1, h->amax, m, h->ne, &why))
+    return fail(h, DGD_EINVAL, why);
+  invalidate_tape(h);
   dgd_status s = upload(h, h->mat, m);
   if (s) return s;
   h->rho_h.assign(rho, rho + h->ne);
+  h->mat_h.swap(m);
   h->law = 1;
   h->have_mat = true;
   return DGD_OK;
@@ -887,6 +962,10 @@ dgd_status dgd_set_material_ivm(dgd_handle* h, const double* rho, const double* 
 dgd_status dgd_set_params(dgd_handle* h, double dt, double alpha_max) {
   if (!h) return DGD_EINVAL;
   if (!(dt > 0.0) || !(alpha_max >= 0.0)) return fail(h, DGD_EINVAL, "dt > 0 and alpha_max >= 0 needed");
+  std::string why;
+  if (h->have_mat && !moduli_admissible(h->law, alpha_max, h->mat_h, h->ne, &why))
+    return fail(h, DGD_EINVAL, why);
+  invalidate_tape(h);
   h->dt = dt;
   h->amax = alpha_max;
   h->have_params = true;
@@ -919,25 +998,25 @@ dgd_status dgd_set_state_from_points(dgd_handle* h, int64_t e0, int64_t count,
   if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
   if (e0 < 0 || count <= 0 || e0 + count > h->ne) return fail(h, DGD_EINVAL, "element range");
   const size_t n = (size_t)count * h->ref.Q * 10;
-  dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+  dgd_status s = dalloc(h, h->tmp, n * sizeof(double));
   if (s) return s;
-  HIPCHK(h, hipMemcpyAsync(h->scratch.p, vals, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->tmp.p, vals, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
   const long long nt = count * 10 * h->ref.L;
   const dim3 g((unsigned)((nt + 255) / 256)), b(256);
   const size_t L = h->ref.L;
   if (h->prec == DGD_FP64)
     hipLaunchKernelGGL((k_project<double>), g, b, 0, h->stream, (long long)count, h->ref.L,
-                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->tmp.p,
                        (double*)h->U9[h->cur].p + (size_t)e0 * 9 * L,
                        (double*)h->Ua[h->cur].p + (size_t)e0 * L);
   else
     hipLaunchKernelGGL((k_project<float>), g, b, 0, h->stream, (long long)count, h->ref.L,
-                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->scratch.p,
+                       h->ref.Q, (const double*)h->Pwd.p, (const double*)h->tmp.p,
                        (float*)h->U9[h->cur].p + (size_t)e0 * 9 * L,
                        (double*)h->Ua[h->cur].p + (size_t)e0 * L);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->scratch.release();
+  h->tmp.release();
   h->have_state = true;
   h->t = 0.0;
   return DGD_OK;
@@ -949,10 +1028,10 @@ dgd_status dgd_set_state(dgd_handle* h, const double* dofs, int on_device) {
   const size_t n = (size_t)h->ne * 10 * h->ref.L;
   const double* src = dofs;
   if (!on_device) {
-    dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+    dgd_status s = dalloc(h, h->tmp, n * sizeof(double));
     if (s) return s;
-    HIPCHK(h, hipMemcpyAsync(h->scratch.p, dofs, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    src = (const double*)h->scratch.p;
+    HIPCHK(h, hipMemcpyAsync(h->tmp.p, dofs, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    src = (const double*)h->tmp.p;
   }
   if (h->prec == DGD_FP64)
     launch_from_f64<double>(h, src);
@@ -960,7 +1039,7 @@ dgd_status dgd_set_state(dgd_handle* h, const double* dofs, int on_device) {
     launch_from_f64<float>(h, src);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (!on_device) h->scratch.release();
+  if (!on_device) h->tmp.release();
   h->have_state = true;
   h->t = 0.0;
   return DGD_OK;
@@ -972,9 +1051,9 @@ dgd_status dgd_get_state(dgd_handle* h, double* dofs, int on_device) {
   const size_t n = (size_t)h->ne * 10 * h->ref.L;
   double* dst = dofs;
   if (!on_device) {
-    dgd_status s = dalloc(h, h->scratch, n * sizeof(double));
+    dgd_status s = dalloc(h, h->tmp, n * sizeof(double));
     if (s) return s;
-    dst = (double*)h->scratch.p;
+    dst = (double*)h->tmp.p;
   }
   if (h->prec == DGD_FP64)
     launch_to_f64<double>(h, dst);
@@ -985,7 +1064,36 @@ dgd_status dgd_get_state(dgd_handle* h, double* dofs, int on_device) {
     HIPCHK(h, hipMemcpyAsync(dofs, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (!on_device) h->scratch.release();
+  if (!on_device) h->tmp.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_get_point_values(dgd_handle* h, int64_t e0, int64_t count, double* vals,
+                                int on_device) {
+  if (!h || !vals) return DGD_EINVAL;
+  if (!h->have_state) return fail(h, DGD_ESTATE, "no state");
+  if (e0 < 0 || count <= 0 || e0 + count > h->ne) return fail(h, DGD_EINVAL, "element range");
+  const size_t L = h->ref.L, Q = h->ref.Q, n = (size_t)count * Q * 10;
+  double* dst = vals;
+  if (!on_device) {
+    dgd_status s = dalloc(h, h->tmp, n * sizeof(double));
+    if (s) return s;
+    dst = (double*)h->tmp.p;
+  }
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (h->prec == DGD_FP64)
+    hipLaunchKernelGGL((k_point_values<double>), g, b, 0, h->stream, (long long)count, (int)L,
+                       (int)Q, (const double*)h->Vd.p, (const double*)h->U9[h->cur].p + e0 * 9 * L,
+                       (const double*)h->Ua[h->cur].p + e0 * L, dst);
+  else
+    hipLaunchKernelGGL((k_point_values<float>), g, b, 0, h->stream, (long long)count, (int)L,
+                       (int)Q, (const double*)h->Vd.p, (const float*)h->U9[h->cur].p + e0 * 9 * L,
+                       (const double*)h->Ua[h->cur].p + e0 * L, dst);
+  HIPCHK(h, hipGetLastError());
+  if (!on_device)
+    HIPCHK(h, hipMemcpyAsync(vals, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!on_device) h->tmp.release();
   return DGD_OK;
 }
 
@@ -1009,6 +1117,7 @@ dgd_status dgd_set_point_sources(dgd_handle* h, int n, const double* xyz, const 
     return fail(h, DGD_EINVAL, "bad source arguments");
   if (stf_kind != DGD_STF_RICKER && stf_kind != DGD_STF_GAUSSIAN)
     return fail(h, DGD_EINVAL, "bad source time function");
+  invalidate_tape(h);
   const int L = h->ref.L;
   std::vector<long long> elem(n);
   std::vector<double> dphi((size_t)n * 3 * L), rhoJ(n), m6(M6, M6 + 6 * (size_t)n),
@@ -1044,6 +1153,7 @@ dgd_status dgd_set_receivers(dgd_handle* h, int nrec, const double* xyz) {
   if (!h) return DGD_EINVAL;
   if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
   if (nrec < 0 || (nrec > 0 && !xyz)) return fail(h, DGD_EINVAL, "bad receiver arguments");
+  invalidate_tape(h);
   const int L = h->ref.L;
   std::vector<long long> elem(nrec);
   std::vector<double> phi((size_t)nrec * L);
@@ -1130,9 +1240,9 @@ dgd_status dgd_energy(dgd_handle* h, double* E) {
   if (!h->have_state || !h->have_mat || !h->have_params)
     return fail(h, DGD_ESTATE, "state, material and params needed");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the energy is that of the continuum-damage law");
-  dgd_status s = dalloc(h, h->scratch, (size_t)(h->ne + 1) * sizeof(double));
+  dgd_status s = dalloc(h, h->tmp, (size_t)(h->ne + 1) * sizeof(double));
   if (s) return s;
-  double* part = (double*)h->scratch.p;
+  double* part = (double*)h->tmp.p;
   if (h->prec == DGD_FP64)
     hipLaunchKernelGGL((k_energy<double>), dim3((unsigned)h->ne), dim3(64), 0, h->stream, h->ne,
                        h->ref.L, h->ref.Q, (const double*)h->Vd.p, (const double*)h->wqd.p,
@@ -1147,7 +1257,7 @@ dgd_status dgd_energy(dgd_handle* h, double* E) {
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(E, part + h->ne, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->scratch.release();
+  h->tmp.release();
   return DGD_OK;
 }
 
@@ -1155,16 +1265,16 @@ dgd_status dgd_wavespeed_change(dgd_handle* h, double* out) {
   if (!h || !out) return DGD_EINVAL;
   if (!h->have_state || !h->have_mat || !h->have_params)
     return fail(h, DGD_ESTATE, "state, material and params needed");
-  dgd_status s = dalloc(h, h->scratch, (size_t)h->ne * sizeof(double));
+  dgd_status s = dalloc(h, h->tmp, (size_t)h->ne * sizeof(double));
   if (s) return s;
   hipLaunchKernelGGL(k_wavespeed, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->stream,
                      h->ne, h->ref.L, (const double*)h->Ua[h->cur].p, (const double*)h->mat.p,
-                     h->amax, h->phi0_mean, h->law, (double*)h->scratch.p);
+                     h->amax, h->phi0_mean, h->law, (double*)h->tmp.p);
   HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipMemcpyAsync(out, h->scratch.p, (size_t)h->ne * sizeof(double), hipMemcpyDeviceToHost,
+  HIPCHK(h, hipMemcpyAsync(out, h->tmp.p, (size_t)h->ne * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->scratch.release();
+  h->tmp.release();
   return DGD_OK;
 }
 
@@ -1217,8 +1327,56 @@ dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
   return DGD_OK;
 }
 
-dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_out,
-                            double* grad_mu0, double* grad_cd) {
+dgd_status dgd_adjoint_step(dgd_handle* h, const double* state_n, double* lam,
+                            const double* dJ_dseis_n, double* grad_mu0, double* grad_cd) {
+  if (!h) return DGD_EINVAL;
+  if (!state_n || !lam) return fail(h, DGD_EINVAL, "null state or adjoint state");
+  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+  if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
+  if (!h->have_mesh || !h->have_mat || !h->have_params)
+    return fail(h, DGD_ESTATE, "mesh, material and params are needed");
+  const size_t E = (size_t)h->ne, L = h->ref.L;
+  dgd_status s;
+  if ((s = alloc_adjoint(h)) || (s = dalloc(h, h->st9, E * 9 * L * h->tsize)) ||
+      (s = dalloc(h, h->sta, E * L * sizeof(double))))
+    return s;
+  const long long n = (long long)(E * 10 * L);
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (h->prec == DGD_FP64) {
+    hipLaunchKernelGGL((k_from_f64<double>), g, b, 0, h->stream, h->ne, h->ref.L, state_n,
+                       (double*)h->st9.p, (double*)h->sta.p);
+    launch_lam_from_f64<double>(h, lam, h->lam[0].p);
+  } else {
+    hipLaunchKernelGGL((k_from_f64<float>), g, b, 0, h->stream, h->ne, h->ref.L, state_n,
+                       (float*)h->st9.p, (double*)h->sta.p);
+    launch_lam_from_f64<float>(h, lam, h->lam[0].p);
+  }
+  if (dJ_dseis_n && h->nrec > 0) {
+    if (h->prec == DGD_FP64)
+      hipLaunchKernelGGL((k_adj_receivers<double>), dim3(1), dim3(3 * L), 0, h->stream, h->nrec,
+                         (int)L, h->kpl, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                         dJ_dseis_n, (double*)h->lam[0].p);
+    else
+      hipLaunchKernelGGL((k_adj_receivers<float>), dim3(1), dim3(3 * L), 0, h->stream, h->nrec,
+                         (int)L, h->kpl, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                         dJ_dseis_n, (float*)h->lam[0].p);
+  }
+  HIPCHK(h, hipGetLastError());
+  // the caller's gradient arrays take the accumulation directly
+  s = dispatch<AdjStepFn>(h, (const void*)h->st9.p, (const double*)h->sta.p,
+                          (const void*)h->lam[0].p, h->lam[1].p, (void*)nullptr,
+                          (const void*)nullptr, (const void*)nullptr, grad_mu0, grad_cd);
+  if (s) return s;
+  if (h->prec == DGD_FP64)
+    launch_lam_to_f64<double>(h, h->lam[1].p, lam);
+  else
+    launch_lam_to_f64<float>(h, h->lam[1].p, lam);
+  HIPCHK(h, hipGetLastError());
+  return DGD_OK;
+}
+
+dgd_status dgd_adjoint_step_host(dgd_handle* h, const double* lam_next, double* lam_out,
+                                 double* grad_mu0, double* grad_cd) {
   if (!h || !lam_next || !lam_out) return DGD_EINVAL;
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
@@ -1227,24 +1385,25 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_o
   dgd_status s = alloc_adjoint(h);
   if (s) return s;
   const size_t n = (size_t)h->ne * 10 * h->ref.L;
-  if ((s = dalloc(h, h->scratch, n * sizeof(double)))) return s;
-  HIPCHK(h, hipMemcpyAsync(h->scratch.p, lam_next, n * sizeof(double), hipMemcpyHostToDevice,
+  if ((s = dalloc(h, h->tmp, n * sizeof(double)))) return s;
+  HIPCHK(h, hipMemcpyAsync(h->tmp.p, lam_next, n * sizeof(double), hipMemcpyHostToDevice,
                            h->stream));
   if (h->prec == DGD_FP64)
-    launch_lam_from_f64<double>(h, (const double*)h->scratch.p, h->lam[0].p);
+    launch_lam_from_f64<double>(h, (const double*)h->tmp.p, h->lam[0].p);
   else
-    launch_lam_from_f64<float>(h, (const double*)h->scratch.p, h->lam[0].p);
+    launch_lam_from_f64<float>(h, (const double*)h->tmp.p, h->lam[0].p);
   HIPCHK(h, hipGetLastError());
   if ((s = dispatch<AdjStepFn>(h, (const void*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
                                (const void*)h->lam[0].p, h->lam[1].p, (void*)nullptr,
-                               (const void*)nullptr, (const void*)nullptr)))
+                               (const void*)nullptr, (const void*)nullptr, (double*)nullptr,
+                               (double*)nullptr)))
     return s;
   if (h->prec == DGD_FP64)
-    launch_lam_to_f64<double>(h, h->lam[1].p, (double*)h->scratch.p);
+    launch_lam_to_f64<double>(h, h->lam[1].p, (double*)h->tmp.p);
   else
-    launch_lam_to_f64<float>(h, h->lam[1].p, (double*)h->scratch.p);
+    launch_lam_to_f64<float>(h, h->lam[1].p, (double*)h->tmp.p);
   HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipMemcpyAsync(lam_out, h->scratch.p, n * sizeof(double), hipMemcpyDeviceToHost,
+  HIPCHK(h, hipMemcpyAsync(lam_out, h->tmp.p, n * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));
   if (grad_mu0)
     HIPCHK(h, hipMemcpyAsync(grad_mu0, h->gmu.p, (size_t)h->ne * sizeof(double),
@@ -1253,7 +1412,7 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* lam_next, double* lam_o
     HIPCHK(h, hipMemcpyAsync(grad_cd, h->gcd.p, (size_t)h->ne * sizeof(double),
                              hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->scratch.release();
+  h->tmp.release();
   return DGD_OK;
 }
 
@@ -1286,6 +1445,7 @@ dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every
   }
   if ((s = dgd_synchronize(h))) return s;
   h->tape = true;
+  h->tape_id = ++h->tapes_made;
   h->tape_steps = nsteps;
   h->tape_every = every;
   return DGD_OK;
@@ -1300,6 +1460,9 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
   const size_t E = (size_t)h->ne, L = h->ref.L;
   const long long nsteps = h->tape_steps, every = h->tape_every;
   const int nrec = h->nrec;
+  for (size_t c = 0; c < h->ck9.size(); ++c)
+    if (h->ck9[c].n != E * 9 * L * h->tsize || h->cka[c].n != E * L * sizeof(double))
+      return fail(h, DGD_ESTATE, "checkpoints do not match the mesh");
   dgd_status s = alloc_adjoint(h);
   if (s) return s;
   if ((s = dalloc(h, h->save9, E * 9 * L * h->tsize)) ||
@@ -1381,7 +1544,7 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       const void* dk = keep_d ? (const void*)((char*)h->segd.p + (size_t)(j - j0) * db) : nullptr;
       const void* ak = keep_d ? (const void*)((char*)h->segacc.p + (size_t)(j - j0) * ab) : nullptr;
       s = dispatch<AdjStepFn>(h, (const void*)u9, ua, (const void*)h->lam[lc].p, h->lam[1 - lc].p,
-                              uz, dk, ak);
+                              uz, dk, ak, (double*)nullptr, (double*)nullptr);
       lc = 1 - lc;
     }
   }
@@ -1395,22 +1558,28 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
   HIPCHK(h, hipMemcpyAsync(grad_cd, h->gcd.p, E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (grad_u0) {
     const size_t n = E * 10 * L;
-    if ((s = dalloc(h, h->scratch, n * sizeof(double)))) return s;
+    if ((s = dalloc(h, h->tmp, n * sizeof(double)))) return s;
     if (h->prec == DGD_FP64)
-      launch_lam_to_f64<double>(h, h->lam[lc].p, (double*)h->scratch.p);
+      launch_lam_to_f64<double>(h, h->lam[lc].p, (double*)h->tmp.p);
     else
-      launch_lam_to_f64<float>(h, h->lam[lc].p, (double*)h->scratch.p);
+      launch_lam_to_f64<float>(h, h->lam[lc].p, (double*)h->tmp.p);
     HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(grad_u0, h->scratch.p, n * sizeof(double), hipMemcpyDeviceToHost,
+    HIPCHK(h, hipMemcpyAsync(grad_u0, h->tmp.p, n * sizeof(double), hipMemcpyDeviceToHost,
                              h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->scratch.release();
+  h->tmp.release();
   h->seg9.release();
   h->sega.release();
   h->seguz.release();
   h->segd.release();
   h->segacc.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_tape_id(const dgd_handle* h, int64_t* id) {
+  if (!h || !id) return DGD_EINVAL;
+  *id = h->tape_id;
   return DGD_OK;
 }
 

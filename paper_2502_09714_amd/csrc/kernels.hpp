@@ -2,12 +2,13 @@
 // one tetrahedron; workgroups are mapped to elements so that each of the eight
 // XCDs walks a contiguous range of elements (neighbours share an L2).
 //
-// k_predict_volume  (paper Appendix A.1 and the volume/source terms of A.2)
+// k_predict  (paper Appendix A.1)
 //   nodal values at t_n -> pointwise CDM tangent -> cell-averaged Jacobians
 //   A*_e = sum_d Theta^-1_ed Bbar^d  (Eq. CKIter-ref)
 //   D^i = -sum_e K^e D^{i-1} A*_e^T, + nodal damage source at i = 1
 //   (Eqs. CKIter-ref-matrix, CKIter-ref-source)
 //   time points U_z = sum_i (tau_z dt)^i/i! D^i  (Eq. taylor_expansion) -> HBM
+// k_volume  (the volume/source terms of Appendix A.2)
 //   volume term dt sum_z gamma_z sum_e Sw^e F^e(U_z) and damage source
 //   (Eqs. 3rd term, rhs term; the nodal projection followed by the stiffness
 //   equals quadrature with Sw = w_q dphi/dxi), partial update written out.
@@ -306,7 +307,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   }
 }
 
-// The predictor's results kept by an earlier launch of k_predict_volume on the
+// The predictor's results kept by an earlier launch of k_predict on the
 // same state (D^1..D^N and the cell-averaged tangent): load them instead of
 // recomputing them.  Leaves S (and dreg) as predictor_stage does, except S.R_.
 template <int N, int P, int ND, bool REGS, bool AW>
@@ -352,38 +353,49 @@ __device__ inline void predictor_restore(const StepArgs<P>& a, long long e,
 // unit), all of them at degree 4 (the register copy would not fit: 45 values
 // per lane).
 template <int N, int P> struct FwdRegs {
-  static constexpr bool value = N <= 3;
+  static constexpr bool value = N <= 3 || P != PREC_F64;
   static constexpr int ND = value ? 1 : N + 1;
 };
 
-// With one LDS derivative buffer the FP32 / BF16 forms fit 21 workgroups per
-// compute unit; asking for five wavefronts per SIMD keeps the registers within
-// that (96 per lane).  The FP64 form is held to ten workgroups by its LDS.
+
+// Launch shapes of the two halves of the element update.  The prediction
+// keeps the derivatives in registers (45 values per lane at degree 4 in FP32)
+// with one LDS buffer; the volume half holds only per-point time integrals.
+template <int N, int P> struct PredWaves {
+  static constexpr int value = !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : 3));
+};
+#ifndef DGD_VOL_WAVES_N4_F32
+#define DGD_VOL_WAVES_N4_F32 2
+#endif
+template <int N, int P> struct VolWaves {
+  static constexpr int value =
+      P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 4 : DGD_VOL_WAVES_N4_F32));
+};
+
+// Prediction (Appendix A.1): Cauchy-Kovalevskaya derivatives of the element
+// and the Taylor sums at the Gauss-Legendre time points (Eq. taylor_expansion),
+// written to HBM in the [l][16] fragment layout (padding rows and columns
+// zero); the derivatives and the cell-averaged tangent also go to Dkeep /
+// Akeep when the adjoint's replay asks for them.
 template <int N, int P, class LW = CdmLaw>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FwdRegs<N, P>::value ? (P == PREC_F64 ? 2 : 5) : 1)))
-void k_predict_volume(StepArgs<P> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PredWaves<N, P>::value)))
+void k_predict(StepArgs<P> a) {
   using PR = Prec<P>;
   using T = typename PR::T;
-  using Acc = typename PR::Acc;
-  constexpr int PA_ = Accurate<P>::value;
-  using PA = Prec<PA_>;
   using DM = Dims<N>;
-  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
-  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
-  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  constexpr int L = DM::L, Nt = DM::Nt;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS);
   constexpr bool REGS = FwdRegs<N, P>::value;
   constexpr int ND = FwdRegs<N, P>::ND;
   using SL = PredLDS<N, P, ND, true>;
-  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
-  static_assert(DS == 16, "time-point states are copied to HBM row by row");
+  constexpr int DPL = SL::DPL;
+  static_assert(SL::DS == 16, "time-point states are copied to HBM row by row");
   __shared__ SL S;
-  T* const sX = S.B;
   T dreg[(N + 1) * DPL];
 
   const int lane = threadIdx.x;
   const long long e = elem_of_block(a.E);
   if (e >= a.E) return;
-  const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   predictor_stage<N, P, ND, REGS, true, LW>(a, e, S, m, lane, dreg);
   // D^i[idx] for idx = lane + 64 j
@@ -401,13 +413,76 @@ void k_predict_volume(StepArgs<P> a) {
       for (int j = 0; j < DPL; ++j) De[(i - 1) * KPL * 16 + lane + 64 * j] = Dv(i, j);
     if (lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
   }
-  T* const sW = S.W;
+  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+#pragma unroll
+  for (int z = 0; z < Nt; ++z) {
+    T cz[N + 1];
+    cz[0] = T(1);
+    const T h = a.tau[z] * (T)a.dt;
+#pragma unroll
+    for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
+      Uzo[z * KPL * 16 + lane + 64 * j] = v;
+    }
+  }
+}
+
+// LDS of the volume half: nodal values / integrands of one 64-point chunk, the
+// damage-rate integrals, Theta^-1, and the partial update before it is stored.
+template <int N, int P> struct VolLDS {
+  using T = typename Prec<P>::T;
+  static constexpr int R = Lds<T>::RS;
+  static constexpr int KPL = round_up(Dims<N>::L, Prec<P>::KS);
+  static constexpr int XS = 64 * R > KPL * 16 ? 64 * R : KPL * 16;
+  T X[XS];
+  T W[KPL * 16];          // the time-point state being evaluated, [l][16]
+  T R_[Dims<N>::NCH * 64];
+};
+
+// Volume and source terms (Appendix A.2, Eqs. 3rd term, rhs term) from the
+// time-point states written by k_predict: stress and damage rate at every
+// (z, q), accumulated as time integrals of velocity and stress per point (the
+// flux is linear in both, so the Jacobian and the stiffness contraction are
+// applied once); volume contraction + source projection; partial update
+// U^n + volume + source written to W (the faces are subtracted later).
+template <int N, int P, class LW = CdmLaw>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VolWaves<N, P>::value)))
+void k_volume(StepArgs<P> a) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  constexpr int PA_ = Accurate<P>::value;
+  using PA = Prec<PA_>;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  using SL = VolLDS<N, P>;
+  constexpr int R = SL::R;
+  __shared__ SL S;
+  T* const sX = S.X;
   T* const sR = S.R_;
 
-  // 4. time points and volume integrands.  The flux is linear in the velocity
-  // and in the stress: only their time integrals sum_z gamma_z v(t_z) and
-  // sum_z gamma_z sigma(t_z) at each volume point are needed (and that of the
-  // damage rate); the Jacobian is applied once, in step 5.
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = (T)a.geo[e * 16 + k];
+  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  // time-point states go through LDS one at a time; the next one's loads are
+  // in flight while the current one is evaluated
+  constexpr int DPL = KPL * 16 / 64;
+  T nxt[DPL];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) nxt[j] = Uze[lane + 64 * j];
+
   T vs[NCH][3], ss[NCH][6], sacc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -417,30 +492,20 @@ void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) ss[c][k] = T(0);
   }
-  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
   for (int z = 0; z < Nt; ++z) {
-    T cz[N + 1];
-    cz[0] = T(1);
-    const T h = a.tau[z] * (T)a.dt;
+    const T g = a.gamma[z];
 #pragma unroll
-    for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
-    // time-point state to LDS and to HBM in the [l][16] fragment layout
-    // (padding rows and columns are zero)
+    for (int j = 0; j < DPL; ++j) S.W[lane + 64 * j] = nxt[j];
+    if (z + 1 < Nt) {
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      T v = T(0);
-#pragma unroll
-      for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
-      sW[lane + 64 * j] = v;
-      Uzo[z * KPL * 16 + lane + 64 * j] = v;
+      for (int j = 0; j < DPL; ++j) nxt[j] = Uze[(z + 1) * KPL * 16 + lane + 64 * j];
     }
     __syncthreads();
-    const T g = a.gamma[z];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, sW, C, lane);
+      wave_gemm_tiles<P, 4, KSL, 16>(a.Vpk + (size_t)c * 4 * KSL * 64, S.W, C, lane);
       store_C<P, 4>(C, sX, 64, T(1), lane);
       __syncthreads();
       const int q = 64 * c + lane;
@@ -459,13 +524,10 @@ void k_predict_volume(StepArgs<P> a) {
     }
   }
 
-  // 5. volume contraction Vol = sum_e Sw^e G^e and damage source integral, with
+  // volume contraction Vol = sum_e Sw^e G^e and damage source integral, with
   // G^e_(ij) = -(Theta^-1_ej v_i + Theta^-1_ei v_j)/2 and
   // G^e_(v_i) = -(1/rho) sum_d Theta^-1_ed sigma_id of the time integrals
   const T ir = T(1) / m.rho;
-  T Ji[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
   Acc Vc[MT];
   zero_C<P, MT>(Vc);
 #pragma unroll
@@ -491,7 +553,7 @@ void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
       for (int p = 0; p < 16; ++p) sX[lane * R + p] = G[p];
       __syncthreads();
-      wave_gemm<P, MT, KSQ>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
+      wave_gemm_tiles<P, MT, KSQ>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
       __syncthreads();
     }
   }
@@ -503,19 +565,17 @@ void k_predict_volume(StepArgs<P> a) {
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
     wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, sR + 64 * c, Vc, lane);
-  store_C<P, MT, DS>(Vc, sW, L, (T)a.dt, lane);
+  store_C<P, MT, 16>(Vc, sX, L, (T)a.dt, lane);
   __syncthreads();
-  // U^n + volume for the nine wave quantities (column 9 keeps the FP64 damage path)
-#pragma unroll
-  for (int j = 0; j < DPL; ++j)
-    if (((lane + 64 * j) & 15) < 9) sW[lane + 64 * j] += Dv(0, j);
-  __syncthreads();
+  // U^n + volume for the nine wave quantities; the damage increment joins the
+  // FP64 damage plane
+  const T* U9 = a.U9 + e * 9 * L;
   T* W9 = a.W9 + e * 9 * L;
   for (int idx = lane; idx < 9 * L; idx += 64) {
     const int p = idx / L, l = idx - p * L;
-    W9[idx] = sW[l * DS + p];
+    W9[idx] = U9[idx] + sX[l * 16 + p];
   }
-  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sW[lane * DS + 9];
+  if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sX[lane * 16 + 9];
 }
 
 
@@ -523,8 +583,12 @@ void k_predict_volume(StepArgs<P> a) {
 // both sides at the shared face points for every time point, LLF (or
 // boundary) flux with the normal of the face's first element, time quadrature.
 // Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
+template <int N, int P> struct FaceWaves {
+  static constexpr int value = N >= 4 ? (P == PREC_F64 ? 2 : 3) : (P == PREC_F64 ? 4 : 7);
+};
+
 template <int N, int P, class LW = CdmLaw>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 4 ? 1 : (P == PREC_F64 ? 4 : 7))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FaceWaves<N, P>::value)))
 void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux) {
   using PR = Prec<P>;
   using T = typename PR::T;
@@ -535,7 +599,7 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   // traces keep only the 10 quantities: an odd row stride reads one row per
   // lane without bank conflicts and halves the LDS of the 16-column layout
   constexpr int R = 11;
-  constexpr int TS = NST * 16 * R;
+  constexpr int TS = Ns * R;            // rows beyond Ns are never stored
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
 
@@ -609,7 +673,7 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
 // Face term and final update (Appendix A.2, Eq. time-integrated): each element
 // lifts the time-integrated flux of its four faces (negated where it is the
 // face's second element: the flux is single valued), scaled by dt |S_f|/|J|,
-// and subtracts it from the partial update of k_predict_volume.
+// and subtracts it from the partial update of k_volume.
 template <int N, int P>
 __global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fmap,
                                                     const typename Prec<P>::T* fflux) {
@@ -757,6 +821,21 @@ __global__ void k_project(long long E, int L, int Q, const double* Pw, const dou
     U9[(e * 9 + p) * L + l] = (T)s;
   else
     Ua[e * L + l] = s;
+}
+
+// point values u(x_q) = sum_l phi_l(xi_q) U_l of elements [0, E) at the volume
+// quadrature points, FP64, out [E][Q][10]
+template <class T>
+__global__ void k_point_values(long long E, int L, int Q, const double* V, const T* U9,
+                               const double* Ua, double* out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * Q * 10) return;
+  const long long e = idx / (Q * 10);
+  const int q = (int)((idx / 10) % Q), p = (int)(idx % 10);
+  double s = 0.0;
+  for (int l = 0; l < L; ++l)
+    s += V[q * L + l] * (p < 9 ? (double)U9[(e * 9 + p) * L + l] : Ua[e * L + l]);
+  out[idx] = s;
 }
 
 template <class T>

@@ -11,6 +11,16 @@
 //      (FP64 accumulators)                                          (i < 4)
 // KS = 4 for FP64 / FP32 (v_mfma_*_16x16x4), KS = 16 for BF16 inputs
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation).
+//
+// BF16 form: a single BF16 product keeps 8 significant bits of every operand
+// (relative rounding 2^-9), which perturbs the discrete operators enough that
+// the state drifts from the FP32/FP64 result by more than 3e-3 within tens
+// of steps.  Each FP32 operand x is therefore split into x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi), and A B is accumulated in FP32 as
+// A_lo B_hi + A_hi B_lo + A_hi B_hi (three matrix-core products; the dropped
+// A_lo B_lo and the rounding of the low parts are about 2^-17 relative).
+// Reference matrices are split on the host, per-element operands when they
+// are loaded (v_cvt_pk_bf16_f32, round to nearest even).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -20,6 +30,30 @@ namespace dgd {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// high and low BF16 parts of four FP32 values (one matrix-core fragment)
+struct __attribute__((aligned(16))) bf16s {
+  bf16x4 hi, lo;
+};
+
+__device__ inline void split_pair(float a, float b, short& ha, short& hb, short& la, short& lb) {
+  const __bf16 h0 = (__bf16)a, h1 = (__bf16)b;
+  const __bf16 l0 = (__bf16)(a - (float)h0), l1 = (__bf16)(b - (float)h1);
+  ha = __builtin_bit_cast(short, h0);
+  hb = __builtin_bit_cast(short, h1);
+  la = __builtin_bit_cast(short, l0);
+  lb = __builtin_bit_cast(short, l1);
+}
+
+__device__ inline bf16s split4(float x0, float x1, float x2, float x3) {
+  bf16s r;
+  short h0, h1, h2, h3, l0, l1, l2, l3;
+  split_pair(x0, x1, h0, h1, l0, l1);
+  split_pair(x2, x3, h2, h3, l2, l3);
+  r.hi = (bf16x4){h0, h1, h2, h3};
+  r.lo = (bf16x4){l0, l1, l2, l3};
+  return r;
+}
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 
@@ -74,29 +108,25 @@ template <> struct Prec<PREC_F32> {
 template <> struct Prec<PREC_BF16> {
   using T = float;
   using Acc = f32x4;
-  using AF = bf16x4;
+  using AF = bf16s;
   static constexpr int KS = 16;
   __device__ static inline int crow(int lane, int i) { return 4 * (lane >> 4) + i; }
-  __device__ static inline Acc mma(AF a, AF b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  __device__ static inline Acc mma(const AF& a, const AF& b, Acc c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
   }
   template <int RS>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
     int k0 = KS * s + 4 * (lane >> 4), n = lane & 15;
-    AF r;
-    r[0] = (short)f32_to_bf16(B[(k0 + 0) * RS + n]);
-    r[1] = (short)f32_to_bf16(B[(k0 + 1) * RS + n]);
-    r[2] = (short)f32_to_bf16(B[(k0 + 2) * RS + n]);
-    r[3] = (short)f32_to_bf16(B[(k0 + 3) * RS + n]);
-    return r;
+    return split4(B[(k0 + 0) * RS + n], B[(k0 + 1) * RS + n], B[(k0 + 2) * RS + n],
+                  B[(k0 + 3) * RS + n]);
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
     int k0 = KS * s + 4 * (lane >> 4);
     const bool on = (lane & 15) == 9;
-    AF r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) r[j] = (short)f32_to_bf16(on ? v[k0 + j] : 0.0f);
-    return r;
+    return split4(on ? v[k0] : 0.0f, on ? v[k0 + 1] : 0.0f, on ? v[k0 + 2] : 0.0f,
+                  on ? v[k0 + 3] : 0.0f);
   }
 };
 
@@ -128,6 +158,21 @@ __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
 #pragma unroll
     for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
   }
+}
+
+// As wave_gemm, one output tile after the other (each B fragment is read once
+// per tile): fewer A fragments in flight, for kernels short of registers.
+template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS>
+__device__ inline void wave_gemm_tiles(const typename Prec<P>::AF* __restrict__ Apk,
+                                       const typename Prec<P>::T* B,
+                                       typename Prec<P>::Acc (&C)[MT], int lane) {
+  using PR = Prec<P>;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s)
+      C[t] = PR::mma(Apk[((size_t)t * KSTEPS + s) * 64 + lane], PR::template loadB<RS>(B, s, lane),
+                     C[t]);
 }
 
 // C += A x B with B[k][n] = (n == 9) ? v[k] : 0 (a vector placed in the damage column)

@@ -22,12 +22,12 @@ def test_work_model_scales_with_elements():
     b = make_workload("c2", n=6, N=3)
     fa, fb = bench.flops_per_launch(a), bench.flops_per_launch(b)
     ba, bb = bench.bytes_per_launch(a, "fp32"), bench.bytes_per_launch(b, "fp32")
-    assert fb["predict_volume"] == 8 * fa["predict_volume"]
-    assert bb["predict_volume"] == 8 * ba["predict_volume"]
-    # about 401 kFLOP per element for the predictor at degree 3
-    assert abs(fa["predict_volume"] / a.ne - 401120) < 1.0
+    for k in ("predict", "volume", "lift_update"):      # element kernels (faces: boundary share)
+        assert fb[k] == 8 * fa[k] and bb[k] == 8 * ba[k]
+    # about 401 kFLOP per element for the prediction and volume terms at degree 3
+    assert abs((fa["predict"] + fa["volume"]) / a.ne - 401120) < 1.0
     # FP64 states move more bytes than FP32 ones
-    assert bench.bytes_per_launch(a, "fp64")["predict_volume"] > ba["predict_volume"]
+    assert bench.bytes_per_launch(a, "fp64")["predict"] > ba["predict"]
 
 
 def test_source_hash_ignores_comments(tmp_path, monkeypatch):
@@ -35,13 +35,20 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     h0 = bench.kernel_source_hash()
     root = tmp_path / "r"
     (root / "paper_2502_09714_amd" / "csrc").mkdir(parents=True)
-    for f in ("kernels.hpp", "physics.hpp", "mfma.hpp"):
+    for f in bench.HASHED_SOURCES:
         src = open(os.path.join(csrc, f)).read()
         if f == "mfma.hpp":
             src = "// an added comment\n/* and a block\n   comment */\n" + src.replace("\n", "  // note\n", 3)
         (root / "paper_2502_09714_amd" / "csrc" / f).write_text(src)
+    build = open(os.path.join(ROOT, "paper_2502_09714_amd", "build.py")).read()
+    (root / "paper_2502_09714_amd" / "build.py").write_text(build)
     monkeypatch.setattr(bench, "ROOT", str(root))
     assert bench.kernel_source_hash() == h0
-    p = root / "paper_2502_09714_amd" / "csrc" / "mfma.hpp"
+    # a code change in the launch code, or another compiler flag, changes it
+    p = root / "paper_2502_09714_amd" / "csrc" / "dgd.hip"
     p.write_text(p.read_text() + "\nint x;\n")
+    assert bench.kernel_source_hash() != h0
+    p.write_text(open(os.path.join(csrc, "dgd.hip")).read())
+    assert bench.kernel_source_hash() == h0
+    (root / "paper_2502_09714_amd" / "build.py").write_text(build.replace('"-O3"', '"-O2"'))
     assert bench.kernel_source_hash() != h0

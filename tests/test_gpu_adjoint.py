@@ -63,7 +63,7 @@ def test_adjoint_step_fp64(name, kw):
     want_u, want_mu, want_cd = step_vjp(S, U, lam)
     sim = _api().from_workload(w, "fp64", state=False)
     sim.set_state(_to_lib(U))
-    got_u, got_mu, got_cd = sim.adjoint_step(_to_lib(lam))
+    got_u, got_mu, got_cd = sim.adjoint_step_host(_to_lib(lam))
     assert rl2(got_u, _to_lib(want_u)) < 1e-8
     assert rl2(got_mu, want_mu.numpy()) < 1e-8
     if float(want_cd.abs().max()) > 0:
@@ -72,6 +72,50 @@ def test_adjoint_step_fp64(name, kw):
         assert np.abs(got_cd).max() == 0.0
     # the state is left as it was
     assert np.array_equal(sim.get_state(), _to_lib(U))
+    sim.close()
+
+
+@pytest.mark.parametrize("name,kw", [STEP_CASES[0], STEP_CASES[3]])
+def test_adjoint_step_device_fp64(name, kw):
+    """dgd_adjoint_step with device tensors: the receiver cotangent of the
+    samples of U^{n+1} joins lambda^{n+1}, the gradients are accumulated onto
+    what the caller's arrays hold, and the solver's own state is unused."""
+    from oracle.sources import Receivers
+    w = make_workload(name, **kw)
+    S = diff_from_workload(w)
+    U = _state_after(S, w, 1)
+    m = w.mesh
+    cent = m["xyz"][m["tets"][[3, 50, 101]]].mean(axis=1)
+    rec = Receivers(S, cent)
+    gen = torch.Generator().manual_seed(8)
+    lam = torch.randn(U.shape, dtype=torch.float64, generator=gen)
+    dl = torch.randn((3, 3), dtype=torch.float64, generator=gen)
+    S.zero_grads()
+    Ul = U.detach().clone().requires_grad_(True)
+    out = S.step(Ul)
+    ((out * lam).sum() + (rec.sample(out) * dl).sum()).backward()
+    want_u = Ul.grad.detach()
+    want_mu, want_cd = S.mat["mu0"].grad.detach(), S.mat["Cd"].grad.detach()
+    sim = _api().from_workload(w, "fp64", state=False)
+    sim.set_receivers(cent)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+    st = dev(_to_lib(U))
+    lam_d = dev(_to_lib(lam))
+    # prior content of the gradient array, of the gradient's own magnitude
+    gmu0 = torch.linspace(-0.5, 0.5, sim.ne, dtype=torch.float64) * float(want_mu.abs().max())
+    gmu = gmu0.clone().cuda()
+    gcd = torch.zeros(sim.ne, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(st, lam_d, dev(dl.numpy()), gmu, gcd)
+    torch.cuda.synchronize()
+    assert rl2(lam_d.cpu().numpy(), _to_lib(want_u)) < 1e-8
+    assert rl2(gmu.cpu().numpy() - gmu0.numpy(), want_mu.numpy()) < 1e-8
+    if float(want_cd.abs().max()) > 0:
+        assert rl2(gcd.cpu().numpy(), want_cd.numpy()) < 1e-8
+    # without the receiver term and gradient arrays
+    lam_d = dev(_to_lib(lam))
+    sim.adjoint_step(st, lam_d)
+    want_u2, _, _ = step_vjp(S, U, lam)
+    assert rl2(lam_d.cpu().numpy(), _to_lib(want_u2)) < 1e-8
     sim.close()
 
 
@@ -98,7 +142,7 @@ def test_adjoint_step_fp32():
     want_u, want_mu, want_cd = step_vjp(S, U, lam)
     sim = _api().from_workload(w, "fp32", state=False)
     sim.set_state(_to_lib(U))
-    got_u, got_mu, got_cd = sim.adjoint_step(_to_lib(lam))
+    got_u, got_mu, got_cd = sim.adjoint_step_host(_to_lib(lam))
     L = _to_lib(lam)
     assert rl2(got_u - L, _to_lib(want_u) - L) < 1e-5
     assert rl2(got_mu, want_mu.numpy()) < 1e-5
@@ -264,7 +308,7 @@ def test_adjoint_errors():
     with pytest.raises(DGDError):
         sim.forward_checkpointed(2, 1)
     with pytest.raises(DGDError):
-        sim.adjoint_step(np.zeros((sim.ne, 10, sim.L)))
+        sim.adjoint_step_host(np.zeros((sim.ne, 10, sim.L)))
     sim.close()
     sim = _api().from_workload(w, "fp64")
     with pytest.raises(DGDError):

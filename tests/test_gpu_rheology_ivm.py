@@ -4,16 +4,22 @@ same law: small cuts of the c1 (periodic, N = 2), c2 (layered basin, free top,
 absorbing sides, N = 3) and c3 (lognormal moduli, N = 4) recipes with the IVM
 parameters of ``workloads.ivm_material`` (damage grows in strained rock and
 heals in the basin, where the storage energy of the initial damage exceeds the
-strain energy).  Bars: relative L2 1e-10 (FP64), 1e-5 (FP32).  The BF16 form
-of this law is not claimed: on the c2 cut it came to 3.3e-3, above the 3e-3
-bar of the CDM law's BF16 form.
+strain energy).  A fourth case keeps Table 2's damage time scale tau_b = 10 s
+(the other cases shorten it so that damage moves within a few steps).  Every
+quantity group is checked by relative L2, pointwise maximum and per element
+(tests/_metrics.py).  Bars: 1e-10 (FP64), 1e-5 (FP32), 3e-3 (BF16 matrix-core
+inputs, FP32 accumulation).
 """
 import numpy as np
 import pytest
 
 from oracle.diagnostics import wavespeed_change as oracle_dcs
 from oracle.step import from_workload as oracle_from
+from oracle.refmat import RefElement
 from workloads import make_workload
+from workloads.configs import ivm_material
+
+from _metrics import assert_within, errors
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +27,7 @@ CASES = {
     "c1": (dict(n=4, N=2), 4),
     "c2": (dict(n=3, N=3), 3),
     "c3": (dict(n=3, N=4), 2),
+    "c2_table2": (dict(n=3, N=3), 3),
 }
 _cache = {}
 
@@ -28,7 +35,10 @@ _cache = {}
 def _oracle(name):
     if name not in _cache:
         kw, nsteps = CASES[name]
-        w = make_workload(name, rheology="ivm", **kw)
+        w = make_workload(name.split("_")[0], rheology="ivm", **kw)
+        if name.endswith("table2"):
+            base = make_workload("c2", **kw).material
+            w.material = ivm_material(base, tau_b=10.0)
         S = oracle_from(w)
         assert S.law.__name__.endswith("ivm")
         U0 = S.project(w.ic)
@@ -47,14 +57,18 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("name,prec,tol", [
     ("c1", "fp64", 1e-10), ("c2", "fp64", 1e-10), ("c3", "fp64", 1e-10),
-    ("c1", "fp32", 1e-5), ("c2", "fp32", 1e-5), ("c3", "fp32", 1e-5)])
+    ("c2_table2", "fp64", 1e-10),
+    ("c1", "fp32", 1e-5), ("c2", "fp32", 1e-5), ("c3", "fp32", 1e-5),
+    ("c2_table2", "fp32", 1e-5),
+    ("c1", "bf16", 3e-3), ("c2", "bf16", 3e-3), ("c3", "bf16", 3e-3)])
 def test_ivm_step_parity(name, prec, tol):
     from paper_2502_09714_amd import api
     w, S, U0, U1, nsteps = _oracle(name)
     want = _to_lib(U1)
     # the damage moved, both ways in the layered cases
     da = U1[:, 0, 9] - U0[:, 0, 9]
-    assert float(da.abs().max()) > 1e-6
+    # tau_b = 10 s: the damage still moves, at a rate 1e5 times smaller
+    assert float(da.abs().max()) > (1e-11 if name.endswith("table2") else 1e-6)
     if name in ("c2", "c3"):
         assert float(da.max()) > 0 and float(da.min()) < 0
     sim = api.from_workload(w, prec, state=False)
@@ -62,8 +76,13 @@ def test_ivm_step_parity(name, prec, tol):
     sim.step(nsteps)
     got = sim.get_state()
     assert np.isfinite(got).all()
-    assert _rel(got, want) < tol, (name, prec, _rel(got, want))
-    assert _rel(got[:, 9], want[:, 9]) < tol
+    e = errors(got, want, RefElement(w.N).V.numpy())
+    print(name, prec, e, flush=True)
+    assert_within(e, tol, f"IVM {name} {prec}")
+    # the damage change itself, not only the damage, to the bar
+    dgot = got[:, 9] - _to_lib(U0)[:, 9]
+    dwant = want[:, 9] - _to_lib(U0)[:, 9]
+    assert _rel(dgot, dwant) < (tol if prec != "fp32" or not name.endswith("table2") else 1e-3)
     if prec == "fp64":
         # damage-only shear-wave-speed change sqrt(1 - abar) - 1
         d = sim.wavespeed_change()

@@ -335,10 +335,16 @@ def _make(name, n, N, nsteps, seed, periodic):
 
 
 def perturbed_material(material, seed=2, rel_mu=0.05, rel_cd=0.2):
-    """Observed-model material for the misfit: mu0 (1 + 0.05 g), C_d (1 + 0.2 g')."""
+    """Observed-model material for the misfit: mu0 (1 + 0.05 g), C_d (1 + 0.2 g').
+    gamma_r keeps its ratio 37/32 to mu0 in the perturbed model (as in every
+    material of the recipes), so that the damaged moduli stay positive up to
+    the clamp alpha_max; the gradient itself is taken with gamma_r fixed."""
     rng = np.random.default_rng(seed)
     ne = material["mu0"].shape[0]
     out = {k: v.copy() for k, v in material.items()}
-    out["mu0"] = material["mu0"] * (1.0 + rel_mu * rng.standard_normal(ne))
+    f = 1.0 + rel_mu * rng.standard_normal(ne)
+    out["mu0"] = material["mu0"] * f
+    if "gamma_r" in out:
+        out["gamma_r"] = material["gamma_r"] * f
     out["Cd"] = material["Cd"] * (1.0 + rel_cd * rng.standard_normal(ne))
     return out
