@@ -259,6 +259,19 @@ dgd_status dgd_clear_seismograms(dgd_handle* h);
 dgd_status dgd_energy(dgd_handle* h, double* E);
 dgd_status dgd_wavespeed_change(dgd_handle* h, double* dcs_over_cs /* ne */);
 
+/* dgd_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving or monitoring loops, harnesses that forbid
+ * hipMalloc): the same energy, computed by the same kernels, but the
+ * per-element partial sums live in a static device buffer of the library
+ * (2^20 doubles, 8 MiB, held by every GPU the library runs on until the
+ * process ends), and the result is written to E, a device pointer to one
+ * double (borrowed).  Queued on the solver's stream without synchronising;
+ * allocates and frees nothing.  EINVAL for a mesh of more than 2^20
+ * elements (use dgd_energy), under the IVM law, or for a NULL pointer;
+ * ESTATE before state, material and params.  All calls on one GPU share the
+ * buffer: calls that overlap in time on one GPU (other streams or host
+ * threads) race and must be serialised by the caller. */
+dgd_status dgd_energy_noalloc(dgd_handle* h, double* E /* device, 1 double */);
 
 /* Instrumentation (no passage of the paper: it measures the method).
  * Per-kernel timing with HIP events recorded on the solver's stream around

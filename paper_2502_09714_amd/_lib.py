@@ -49,6 +49,7 @@ _SIGS = {
     "dgd_num_seismogram_steps": (ctypes.c_int, [H, c_i64p]),
     "dgd_clear_seismograms": (ctypes.c_int, [H]),
     "dgd_energy": (ctypes.c_int, [H, c_dp]),
+    "dgd_energy_noalloc": (ctypes.c_int, [H, ctypes.c_void_p]),
     "dgd_wavespeed_change": (ctypes.c_int, [H, c_dp]),
     "dgd_get_time_point_states": (ctypes.c_int, [H, c_dp]),
     "dgd_set_profiling": (ctypes.c_int, [H, ctypes.c_int]),

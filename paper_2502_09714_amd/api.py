@@ -181,6 +181,13 @@ class Simulation:
         self._chk(self._L.dgd_energy(self.h, ctypes.byref(e)))
         return e.value
 
+    def energy_noalloc(self, out):
+        """dgd_energy_noalloc: the energy written to ``out``, a float64 torch
+        tensor of one element on the device, without allocating."""
+        import torch
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() == 1
+        self._chk(self._L.dgd_energy_noalloc(self.h, ctypes.c_void_p(out.data_ptr())))
+
     def wavespeed_change(self):
         out = np.zeros(self.ne)
         self._chk(self._L.dgd_wavespeed_change(self.h, _dp(out)))

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -15,7 +17,33 @@
 
 using namespace dgd;
 
+// Partial energy sums of dgd_energy_noalloc (one per element), for callers
+// that cannot allocate device memory.  Every GPU the library runs on holds its
+// own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr long long kNoallocMaxElems = 1LL << 20;
+static __device__ __align__(256) double scratch[kNoallocMaxElems];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;   // device -> address of its scratch
+
+// device address of `scratch` on the current device (looked up once per device)
+hipError_t scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = (double*)p;
+  *out = (double*)p;
+  return hipSuccess;
+}
 
 struct Bf16x8 { uint16_t v[8]; };   // high parts of four values, then their low parts
 
@@ -39,6 +67,7 @@ struct DevBuf {
 struct dgd_handle {
   int N = 0, prec = 0, device = 0;
   hipStream_t stream = nullptr;
+  double* noalloc_part = nullptr;   // this device's static partial-sum buffer
   std::string err;
   RefData ref;
   size_t tsize = 8;  // bytes of the working type
@@ -716,7 +745,8 @@ dgd_status dgd_create(int N, int precision, void* hip_stream, dgd_handle** out) 
   h->prec = precision;
   h->stream = (hipStream_t)hip_stream;
   h->tsize = precision == DGD_FP64 ? 8 : 4;
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      scratch_address(h->device, &h->noalloc_part) != hipSuccess) {
     delete h;
     return DGD_EDEVICE;
   }
@@ -1258,6 +1288,32 @@ dgd_status dgd_energy(dgd_handle* h, double* E) {
   HIPCHK(h, hipMemcpyAsync(E, part + h->ne, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->tmp.release();
+  return DGD_OK;
+}
+
+dgd_status dgd_energy_noalloc(dgd_handle* h, double* E) {
+  if (!h || !E) return DGD_EINVAL;
+  if (h->ne > kNoallocMaxElems)
+    return fail(h, DGD_EINVAL,
+                "dgd_energy_noalloc takes at most " + std::to_string(kNoallocMaxElems) +
+                    " elements (its static partial-sum buffer); this mesh has " +
+                    std::to_string(h->ne) + ": use dgd_energy");
+  if (!h->have_state || !h->have_mat || !h->have_params)
+    return fail(h, DGD_ESTATE, "state, material and params needed");
+  if (h->law != 0) return fail(h, DGD_EINVAL, "the energy is that of the continuum-damage law");
+  double* part = h->noalloc_part;   // every entry [0, ne) is written before it is read
+  if (h->prec == DGD_FP64)
+    hipLaunchKernelGGL((k_energy<double>), dim3((unsigned)h->ne), dim3(64), 0, h->stream, h->ne,
+                       h->ref.L, h->ref.Q, (const double*)h->Vd.p, (const double*)h->wqd.p,
+                       (const double*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                       (const double*)h->geo.p, (const double*)h->mat.p, h->amax, 1e-15, part);
+  else
+    hipLaunchKernelGGL((k_energy<float>), dim3((unsigned)h->ne), dim3(64), 0, h->stream, h->ne,
+                       h->ref.L, h->ref.Q, (const double*)h->Vd.p, (const double*)h->wqd.p,
+                       (const float*)h->U9[h->cur].p, (const double*)h->Ua[h->cur].p,
+                       (const double*)h->geo.p, (const double*)h->mat.p, h->amax, 1e-15, part);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, h->stream, h->ne, part, E);
+  HIPCHK(h, hipGetLastError());
   return DGD_OK;
 }
 
