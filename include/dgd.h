@@ -190,6 +190,24 @@ dgd_status dgd_get_point_values(dgd_handle* h, int64_t e0, int64_t count, double
 dgd_status dgd_set_time(dgd_handle* h, double t);
 dgd_status dgd_get_time(const dgd_handle* h, double* t);
 
+/* Predictor of the step (Appendix A.1).  DGD_PREDICT_CK (the default): the
+ * linearised Cauchy-Kovalevskaya recursion at the cell-averaged Jacobian
+ * (Eqs. CKIter, CKIter-ref-matrix, CKIter-ref-source) and its Taylor sums.
+ * DGD_PREDICT_PICARD: the discrete Picard iteration the paper's Section 5.1
+ * names as the replacement that keeps high order for nonlinear rheologies.
+ * Reading (the paper gives no formulas): the element-local evolution that
+ * the recursion differentiates, dU/dt = R(U) = -sum_e K^e P G^e(U) + P r(U)
+ * in strong form with the pointwise flux and damage rate of the current
+ * iterate (no linearisation), is solved on the N+1 Gauss-Legendre time points
+ * by `iterations` Picard sweeps of the collocation equations
+ * U_z = U^n + dt sum_j Om_zj R(U_j), Om_zj = int_0^tau_z l_j, from U_z = U^n
+ * (iterations = 0 means N + 1).  The corrector is unchanged.  The discrete
+ * adjoint is that of the Cauchy-Kovalevskaya predictor: its calls return
+ * EINVAL under this one.  EINVAL for another kind or iterations < 0.  Drops
+ * a checkpointed run. */
+typedef enum { DGD_PREDICT_CK = 0, DGD_PREDICT_PICARD = 1 } dgd_predictor;
+dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations);
+
 /* Point moment-tensor sources.  The paper drives its Gorkha runs with a
  * kinematic finite-fault source (Section 4.1) without printing how it enters
  * the discrete system; the reading used here is the equivalent body force

@@ -14,6 +14,7 @@ DGD_OK = 0
 STATUS = {0: "DGD_OK", -1: "DGD_EINVAL", -2: "DGD_ENOMEM", -3: "DGD_EDEVICE",
           -4: "DGD_ESTATE", -5: "DGD_ENUMERIC"}
 FP64, FP32, BF16 = 0, 1, 2
+PREDICT_CK, PREDICT_PICARD = 0, 1
 
 _lib = None
 
@@ -40,6 +41,7 @@ _SIGS = {
                                             ctypes.c_int]),
     "dgd_set_time": (ctypes.c_int, [H, ctypes.c_double]),
     "dgd_get_time": (ctypes.c_int, [H, c_dp]),
+    "dgd_set_predictor": (ctypes.c_int, [H, ctypes.c_int, ctypes.c_int]),
     "dgd_set_point_sources": (ctypes.c_int, [H, ctypes.c_int, c_dp, c_dp, c_dp, c_dp, ctypes.c_int]),
     "dgd_set_receivers": (ctypes.c_int, [H, ctypes.c_int, c_dp]),
     "dgd_step": (ctypes.c_int, [H, ctypes.c_int64]),

@@ -141,6 +141,12 @@ class Simulation:
         self._chk(self._L.dgd_get_time(self.h, ctypes.byref(t)))
         return t.value
 
+    def set_predictor(self, kind="ck", iterations=0):
+        """Predictor of the step: "ck" (linearised Cauchy-Kovalevskaya) or
+        "picard" (Picard iteration, `iterations` sweeps, 0 = N + 1)."""
+        k = {"ck": 0, "picard": 1}[kind] if isinstance(kind, str) else int(kind)
+        self._chk(self._L.dgd_set_predictor(self.h, k, int(iterations)))
+
     def set_point_sources(self, xyz, M6, t_onset, stf_param, stf_kind):
         xyz = _f64(xyz, (-1, 3))
         n = xyz.shape[0]

@@ -72,7 +72,9 @@ struct dgd_handle {
   RefData ref;
   size_t tsize = 8;  // bytes of the working type
   // reference data on the device
-  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Vd, wqd, Pwd, betad;
+  DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Vd, wqd, Pwd, betad, KPpk;
+  int predictor = 0;      // 0: linearised Cauchy-Kovalevskaya, 1: Picard iteration
+  int picard_iters = 0;
   int kpl = 0;  // padded mode count of the time-point state layout
   double inv_wsum = 6.0, phi0_mean = 0.0;
   // mesh and material
@@ -118,7 +120,8 @@ struct dgd_handle {
                      &conn, &mat, &faces, &fmap, &fflux, &U9[0], &U9[1], &Ua[0], &Ua[1], &Uz, &flag, &tmp,
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &gtr, &gmuf, &lzf, &gmu, &gcd, &adjW9,
-                     &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea, &st9, &sta};
+                     &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea, &st9, &sta,
+                     &KPpk};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
@@ -218,7 +221,7 @@ dgd_status build_packed(dgd_handle* h) {
   const RefData& r = h->ref;
   constexpr int KS = Prec<P>::KS, L = DM::L, Q = DM::Q, Ns = DM::Ns;
   constexpr int KPL = round_up(L, KS), KSL = KPL / KS, KPN = round_up(Ns, KS), KSN = KPN / KS;
-  std::vector<AF> v, k, s, f, lf;
+  std::vector<AF> v, k, s, f, lf, kp;
   for (int c = 0; c < DM::NCH; ++c)
     append(v, pack_A<P>(
                   [&](int m, int kk) {
@@ -233,13 +236,20 @@ dgd_status build_packed(dgd_handle* h) {
       },
       DM::MT, 3 * KSL);
   for (int e = 0; e < 3; ++e)
-    for (int c = 0; c < DM::NCH; ++c)
+    for (int c = 0; c < DM::NCH; ++c) {
       append(s, pack_A<P>(
                     [&](int m, int kk) {
                       int q = 64 * c + kk;
                       return (m < L && q < Q) ? r.Sw[((size_t)e * L + m) * Q + q] : 0.0;
                     },
                     DM::MT, 64 / KS));
+      append(kp, pack_A<P>(
+                     [&](int m, int kk) {
+                       int q = 64 * c + kk;
+                       return (m < L && q < Q) ? r.KP[((size_t)e * L + m) * Q + q] : 0.0;
+                     },
+                     DM::MT, 64 / KS));
+    }
   for (int ff = 0; ff < 4; ++ff)
     for (int sp = 0; sp < 6; ++sp) {
       const double* F = &r.F[((size_t)ff * 6 + sp) * Ns * L];
@@ -264,7 +274,8 @@ dgd_status build_packed(dgd_handle* h) {
                    DM::MT, KSQA));
   dgd_status st;
   if ((st = upload(h, h->Vpk, v)) || (st = upload(h, h->Kpk, k)) || (st = upload(h, h->Spk, s)) ||
-      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)))
+      (st = upload(h, h->Fpk, f)) || (st = upload(h, h->Lpk, lf)) || (st = upload(h, h->Ppk, pp)) ||
+      (st = upload(h, h->KPpk, kp)))
     return st;
   if constexpr (P != PREC_BF16) {
     // transposed operators of the discrete adjoint
@@ -381,10 +392,22 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
   for (long long it = 0; it < nsteps; ++it) {
     StepArgs<P> a = make_args<N, P>(h);
     timed(h, 0, [&] {
-      if (ivm)
+      if (h->predictor == 1) {
+        PicardArgs<P> pa;
+        pa.KPpk = (const typename Prec<P>::AF*)h->KPpk.p;
+        pa.iters = h->picard_iters > 0 ? h->picard_iters : N + 1;
+        for (int z = 0; z < 8; ++z)
+          for (int j = 0; j < 8; ++j)
+            pa.om[z][j] = (z < h->ref.Nt && j < h->ref.Nt) ? (T)h->ref.Om[z * h->ref.Nt + j] : T(0);
+        if (ivm)
+          hipLaunchKernelGGL((k_predict_picard<N, P, IvmLaw>), grid, block, 0, h->stream, a, pa);
+        else
+          hipLaunchKernelGGL((k_predict_picard<N, P, CdmLaw>), grid, block, 0, h->stream, a, pa);
+      } else if (ivm) {
         hipLaunchKernelGGL((k_predict<N, P, IvmLaw>), grid, block, 0, h->stream, a);
-      else
+      } else {
         hipLaunchKernelGGL((k_predict<N, P, CdmLaw>), grid, block, 0, h->stream, a);
+      }
     });
     timed(h, 9, [&] {
       if (ivm)
@@ -1139,6 +1162,16 @@ dgd_status dgd_get_time(const dgd_handle* h, double* t) {
   return DGD_OK;
 }
 
+dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations) {
+  if (!h) return DGD_EINVAL;
+  if ((kind != DGD_PREDICT_CK && kind != DGD_PREDICT_PICARD) || iterations < 0)
+    return fail(h, DGD_EINVAL, "predictor kind 0 or 1 and iterations >= 0 needed");
+  invalidate_tape(h);
+  h->predictor = kind;
+  h->picard_iters = iterations;
+  return DGD_OK;
+}
+
 dgd_status dgd_set_point_sources(dgd_handle* h, int n, const double* xyz, const double* M6,
                                  const double* t_onset, const double* stf_param, int stf_kind) {
   if (!h) return DGD_EINVAL;
@@ -1389,6 +1422,8 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* state_n, double* lam,
   if (!state_n || !lam) return fail(h, DGD_EINVAL, "null state or adjoint state");
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
+  if (h->predictor != 0)
+    return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
   if (!h->have_mesh || !h->have_mat || !h->have_params)
     return fail(h, DGD_ESTATE, "mesh, material and params are needed");
   const size_t E = (size_t)h->ne, L = h->ref.L;
@@ -1436,6 +1471,8 @@ dgd_status dgd_adjoint_step_host(dgd_handle* h, const double* lam_next, double* 
   if (!h || !lam_next || !lam_out) return DGD_EINVAL;
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
+  if (h->predictor != 0)
+    return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
   if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
     return fail(h, DGD_ESTATE, "mesh, material, params and state are needed");
   dgd_status s = alloc_adjoint(h);
@@ -1477,6 +1514,8 @@ dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every
   if (nsteps < 1 || every < 1) return fail(h, DGD_EINVAL, "nsteps >= 1 and every >= 1 needed");
   if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
+  if (h->predictor != 0)
+    return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
   if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
     return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
   release_tape(h);

@@ -431,6 +431,157 @@ void k_predict(StepArgs<P> a) {
   }
 }
 
+// ---- Picard-iteration predictor --------------------------------------------------
+// The alternative to the linearised Cauchy-Kovalevskaya prediction named in the
+// paper's Discussion (Section 5.1).  The element-local evolution that the
+// recursion differentiates, taken in strong form without linearisation,
+//   dU/dt = R(U) = - sum_e KP^e G^e(U) + Pw r(U),
+//   G^e = sum_d Theta^-1_ed F^d(V U) at the volume points, KP^e = K^e Pw,
+// is solved on the Gauss-Legendre time points by Picard iteration of the
+// collocation equations U_z = U^n + dt sum_j Om_zj R(U_j), from U_z = U^n.
+template <int P> struct PicardArgs {
+  using T = typename Prec<P>::T;
+  const typename Prec<P>::AF* KPpk;   // KP^e per 64-point chunk, packed like Spk
+  int iters;
+  T om[8][8];
+};
+
+template <int N, int P> struct PicardLDS {
+  using T = typename Prec<P>::T;
+  static constexpr int R = Lds<T>::RS;
+  static constexpr int KPL = round_up(Dims<N>::L, Prec<P>::KS);
+  static constexpr int XS = 64 * R > KPL * 16 ? 64 * R : KPL * 16;
+  T X[XS];                            // nodal values / integrands of one chunk, R(U_j)
+  T Uz[Dims<N>::Nt][KPL * 16];        // the current iterate U_z, [l][16]
+  T R_[64];                           // damage rate at the points of one chunk
+  T J[9];                             // Theta^-1
+};
+
+template <int N, int P> struct PicardWaves {
+  static constexpr int value = P == PREC_F64 ? (N <= 2 ? 3 : 2) : (N <= 2 ? 4 : (N == 3 ? 3 : 2));
+};
+
+template <int N, int P, class LW = CdmLaw>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PicardWaves<N, P>::value)))
+void k_predict_picard(StepArgs<P> a, PicardArgs<P> pa) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  constexpr int PA_ = Accurate<P>::value;
+  using PA = Prec<PA_>;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  constexpr int DPL = KPL * 16 / 64;
+  using SL = PicardLDS<N, P>;
+  constexpr int R = SL::R;
+  __shared__ SL S;
+  T* const sX = S.X;
+
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
+  const T ir = T(1) / m.rho;
+  const T dt = (T)a.dt;
+
+  // U^n in the [l][16] layout, lane + 64 j (padding rows and columns zero)
+  T u0[DPL];
+  const T* U9 = a.U9 + e * 9 * L;
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+    u0[j] = (l < L && p < 10) ? (p < 9 ? U9[p * L + l] : (T)a.Ua[e * L + l]) : T(0);
+  }
+#pragma unroll
+  for (int z = 0; z < Nt; ++z)
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) S.Uz[z][lane + 64 * j] = u0[j];
+
+  T un[Nt][DPL];                      // the next iterate, accumulated
+  for (int it = 0; it < pa.iters; ++it) {
+#pragma unroll
+    for (int z = 0; z < Nt; ++z)
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) un[z][j] = u0[j];
+    for (int jt = 0; jt < Nt; ++jt) {
+      __syncthreads();
+      Acc Rc[MT];
+      zero_C<P, MT>(Rc);
+#pragma unroll 1
+      for (int c = 0; c < NCH; ++c) {
+        // nodal values of U_jt at the chunk's points, pointwise flux as G^e
+        // of the reference directions, damage rate
+        Acc C[4];
+        zero_C<P, 4>(C);
+        wave_gemm_tiles<P, 4, KSL, 16>(a.Vpk + (size_t)c * 4 * KSL * 64, S.Uz[jt], C, lane);
+        store_C<P, 4>(C, sX, 64, T(1), lane);
+        __syncthreads();
+        const bool on = 64 * c + lane < Q;
+        T u[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
+        T sig[6];
+        const T r = LW::stress_rate(u, m, law, sig);
+        S.R_[lane] = on ? r : T(0);
+        // R += -sum_e KP^e G^e over this chunk, direction by direction
+#pragma unroll 1
+        for (int ee = 0; ee < 3; ++ee) {
+          T Jr[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Jr[d] = S.J[ee * 3 + d];
+          T G[9];
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+            const int ii = kVI[p], jj = kVJ[p];
+            G[p] = T(-0.5) * (Jr[jj] * u[6 + ii] + Jr[ii] * u[6 + jj]);
+          }
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) {
+            T t = T(0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) t += Jr[d] * sig[sym_idx(ii, d)];
+            G[6 + ii] = -ir * t;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int p = 0; p < 16; ++p) sX[lane * R + p] = (on && p < 9) ? -G[p] : T(0);
+          __syncthreads();
+          wave_gemm_tiles<P, MT, KSQ>(pa.KPpk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Rc,
+                                      lane);
+        }
+        // + Pw r in the damage column
+        wave_gemm_col9<PA_, MT, KSQA>(a.Ppk + (size_t)c * MT * KSQA * 64, S.R_, Rc, lane);
+        __syncthreads();
+      }
+      // the next iterate: U_z += dt Om_z,jt R(U_jt) for every z
+      store_C<P, MT, 16>(Rc, sX, KPL, T(1), lane);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) {
+        const int idx = lane + 64 * j;
+        const T rv = (idx & 15) < 10 ? sX[idx] : T(0);
+#pragma unroll
+        for (int z = 0; z < Nt; ++z) un[z][j] += dt * pa.om[z][jt] * rv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < Nt; ++z)
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) S.Uz[z][lane + 64 * j] = un[z][j];
+  }
+  __syncthreads();
+  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+#pragma unroll
+  for (int z = 0; z < Nt; ++z)
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) Uzo[z * KPL * 16 + lane + 64 * j] = S.Uz[z][lane + 64 * j];
+}
+
 // LDS of the volume half: nodal values / integrands of one 64-point chunk, the
 // damage-rate integrals, Theta^-1, and the partial update before it is stored.
 template <int N, int P> struct VolLDS {

@@ -182,6 +182,38 @@ RefData build_reference(int N) {
         basis_eval(N, xi, phi.data(), nullptr);
         for (int l = 0; l < L; ++l) r.F[(((size_t)f * 6 + s) * Ns + i) * L + l] = phi[l];
       }
+  // strong-form derivative of a projected field: KP[e] = K[e] Pw
+  r.KP.assign((size_t)3 * L * Q, 0.0);
+  for (int e = 0; e < 3; ++e)
+    for (int k = 0; k < L; ++k)
+      for (int l = 0; l < L; ++l) {
+        const double kk = r.K[((size_t)e * L + k) * L + l];
+        for (int q = 0; q < Q; ++q) r.KP[((size_t)e * L + k) * Q + q] += kk * r.Pw[(size_t)l * Q + q];
+      }
+  // Om[z][j] = int_0^{tau_z} l_j(s) ds for the Lagrange polynomials l_j of the
+  // time points (monomial coefficients built factor by factor)
+  r.Om.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    std::vector<double> c(1, 1.0);
+    for (int k = 0; k < n; ++k) {
+      if (k == j) continue;
+      const double d = r.tau[j] - r.tau[k];
+      std::vector<double> nc(c.size() + 1, 0.0);
+      for (size_t i = 0; i < c.size(); ++i) {
+        nc[i + 1] += c[i] / d;
+        nc[i] -= c[i] * r.tau[k] / d;
+      }
+      c.swap(nc);
+    }
+    for (int z = 0; z < n; ++z) {
+      double acc = 0.0, pw = r.tau[z];
+      for (size_t i = 0; i < c.size(); ++i) {
+        acc += c[i] / (double)(i + 1) * pw;
+        pw *= r.tau[z];
+      }
+      r.Om[(size_t)z * n + j] = acc;
+    }
+  }
   std::vector<Mode> ms = modes(N);
   for (auto& m : ms) r.deg.push_back(m.i + m.j + m.k);
   return r;

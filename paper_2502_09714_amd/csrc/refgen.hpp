@@ -13,6 +13,9 @@
 //   F[f][s][i][l] = phi_l(xi^f(eta_i permuted by s)) face traces, s = permutation of
 //                   the face vertices that puts the rule on the face in global order
 //   beta[i], tau[z], gamma[z]                      face and time weights
+//   KP[e][k][q] = sum_l K[e][k][l] Pw[l][q]        strong-form derivative of a projected field
+//   Om[z][j]   = int_0^tau_z l_j(s) ds             time integration of the Lagrange
+//                                                  polynomials of the time points
 #pragma once
 #include <vector>
 
@@ -30,6 +33,8 @@ struct RefData {
   std::vector<double> Pw;     // L*Q
   std::vector<double> Sw;     // 3*L*Q
   std::vector<double> K;      // 3*L*L
+  std::vector<double> KP;     // 3*L*Q
+  std::vector<double> Om;     // Nt*Nt
   std::vector<double> F;      // 4*6*Ns*L
   std::vector<int> deg;       // L total degrees
 };
