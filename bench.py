@@ -205,13 +205,51 @@ def run_adjoint(w, prec, steps, every, observed=False):
     ms, launches = sim.get_kernel_times()
     sim.set_profiling(False)
     sim.close()
-    return {"workload": f"{w.name}: {w.ne} tets, N={w.N}, {len(seis[0])} receivers",
-            "forward_s": t1 - t0, "backward_s": t3 - t2,
-            "backward_over_forward": (t3 - t2) / (t1 - t0),
-            "backward_kernel_ms_per_step": {k: float(ms[i]) / steps for i, k in enumerate(KERNELS)
-                                            if launches[i] > 0},
-            "steps": steps, "checkpoint_every": every,
-            "finite": bool(np.isfinite(gmu).all() and np.isfinite(gcd).all())}
+    out = {"workload": f"{w.name}: {w.ne} tets, N={w.N}, {len(seis[0])} receivers",
+           "forward_s": t1 - t0, "backward_s": t3 - t2,
+           "backward_over_forward": (t3 - t2) / (t1 - t0),
+           "backward_kernel_ms_per_step": {k: float(ms[i]) / steps for i, k in enumerate(KERNELS)
+                                           if launches[i] > 0},
+           "steps": steps, "checkpoint_every": every,
+           "finite": bool(np.isfinite(gmu).all() and np.isfinite(gcd).all())}
+    return out, (gmu, gcd, obs, U0, base)
+
+
+def fd_check(w, steps, grads, nelem, seed=31):
+    """Central differences (relative step 1e-4) of the FP64 forward misfit on
+    nelem elements drawn at random, against the adjoint gradients."""
+    import numpy as np
+    from paper_2502_09714_amd.api import from_workload
+    gmu, gcd, obs, U0, base = grads
+    sim = from_workload(w, "fp64", state=False)
+    if sim.nrec == 0:
+        m = w.mesh
+        sim.set_receivers(m["xyz"][m["tets"][[0, w.ne // 3, w.ne // 2, (2 * w.ne) // 3]]].mean(axis=1))
+    sim.set_check_interval(1 << 40)
+
+    def misfit(mat):
+        sim.set_material(**mat)
+        sim.set_state(U0)
+        sim.set_time(0.0)
+        sim.clear_seismograms()
+        sim.step(steps)
+        return 0.5 * float(((sim.get_seismograms() - obs) ** 2).sum())
+
+    idx = [int(e) for e in np.random.default_rng(seed).choice(w.ne, nelem, replace=False)]
+    rows = []
+    for which, g in (("mu0", gmu), ("Cd", gcd)):
+        for e in idx:
+            h = 1e-4 * base[which][e]
+            mp = {k: v.copy() for k, v in base.items()}
+            mp[which][e] += h
+            jp = misfit(mp)
+            mp[which][e] -= 2 * h
+            jm = misfit(mp)
+            fd = (jp - jm) / (2 * h)
+            rows.append({"param": which, "element": e, "adjoint": float(g[e]), "fd": fd,
+                         "rel_diff": abs(float(g[e]) - fd) / max(abs(fd), 1e-300)})
+    sim.close()
+    return rows
 
 
 def rel_l2(a, b):
@@ -373,9 +411,10 @@ def main():
                     help="precisions whose checkpointed adjoint is timed on the step workload "
                          "('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
-    ap.add_argument("--adjoint-workload", default="c4",
-                    help="workload of the full-length adjoint timing ('' for none)")
-    ap.add_argument("--adjoint-workload-precisions", default="fp32")
+    ap.add_argument("--adjoint-runs", default="c4:400:20,c3:200:20",
+                    help="checkpointed FP32 adjoint runs workload:steps:every ('' for none)")
+    ap.add_argument("--adjoint-fd", type=int, default=0,
+                    help="central differences on this many elements for the last adjoint run")
     ap.add_argument("--ivm-precisions", default="fp32",
                     help="precisions of the IVM-rheology step timing ('' for none)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -465,17 +504,21 @@ def main():
             line["ivm"] = {"error": f"{type(exc).__name__}: {exc}"}
         print(f"ivm: {line['ivm']}", file=sys.stderr, flush=True)
     for p in [q.strip() for q in args.adjoint_precisions.split(",") if q.strip()]:
-        a = run_adjoint(w, p, args.steps, args.checkpoint_every)
+        a, _ = run_adjoint(w, p, args.steps, args.checkpoint_every)
         print(f"adjoint {p}: {a}", file=sys.stderr, flush=True)
         line[f"adjoint_{p}"] = a
-    if args.adjoint_workload:
-        # the differentiation-form workload: 82,944 tets, N=3, point source,
-        # 16 receivers, 400 steps with checkpoints every 20, FP32
-        wa = make_workload(args.adjoint_workload)
-        for p in [q.strip() for q in args.adjoint_workload_precisions.split(",") if q.strip()]:
-            a = run_adjoint(wa, p, wa.nsteps, 20, observed=True)
-            print(f"adjoint {args.adjoint_workload} {p}: {a}", file=sys.stderr, flush=True)
-            line[f"adjoint_{args.adjoint_workload}_{p}"] = a
+    runs = [r.split(":") for r in args.adjoint_runs.split(",") if r.strip()]
+    for i, (name, steps, every) in enumerate(runs):
+        # checkpointed FP32 misfit gradient (mu0, C_d) against a run with the
+        # perturbed model: c4 is the differentiation-form workload (82,944
+        # tets, N=3, point source, 16 receivers, 400 steps, checkpoints every
+        # 20), c3 the degree-4 precision-form mesh (1,572,864 tets)
+        wa = make_workload(name)
+        a, grads = run_adjoint(wa, "fp32", int(steps), int(every), observed=True)
+        if args.adjoint_fd and i == len(runs) - 1:
+            a["fd_check"] = fd_check(wa, int(steps), grads, args.adjoint_fd)
+        print(f"adjoint {name} fp32: {a}", file=sys.stderr, flush=True)
+        line[f"adjoint_{name}_fp32"] = a
     if args.error_workload:
         eprecs = [q.strip() for q in args.error_precisions.split(",") if q.strip()]
         line["precision_errors"] = precision_errors(args.error_workload, args.error_steps, eprecs)

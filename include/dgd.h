@@ -208,6 +208,38 @@ dgd_status dgd_get_time(const dgd_handle* h, double* t);
 typedef enum { DGD_PREDICT_CK = 0, DGD_PREDICT_PICARD = 1 } dgd_predictor;
 dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations);
 
+/* Clustered local time stepping.  The paper steps every element with one
+ * global step and names local time stepping as the missing piece for its
+ * nonlinear runs (Section 5.1); it gives no scheme.  Reading (rate-2
+ * clusters): element e steps with dt0 2^cluster[e] (cluster 0..7, face
+ * neighbours at most one cluster apart, EINVAL otherwise).  A step of cluster
+ * c over [t, t + dt_c] predicts its elements at t (Cauchy-Kovalevskaya, the
+ * derivatives kept), lets cluster c-1 take its two steps inside, then
+ * corrects: faces to clusters >= c take the flux at the cluster's time
+ * points with the neighbour's Taylor expansion evaluated there; faces to
+ * cluster c-1 take the flux integrals that cluster computed over its two
+ * steps; volume and source terms and the update are those of the global
+ * step.  Every face flux is computed once, by the finer side, so the wave
+ * quantities are conserved across cluster boundaries; one cluster is the
+ * global step.
+ * dgd_set_clusters: cluster per element (host, ne, copied) and dt0 (> 0);
+ * NULL removes the clusters.  ESTATE before the mesh.  Drops a checkpointed
+ * run.
+ * dgd_make_clusters: proposes clusters from each element's admissible step
+ * cfl 2 r_in / ((2N+1) c_p) (intact moduli): dt0 = the smallest, cluster =
+ * floor(log2(dt_e / dt0)) capped at max_clusters - 1 and lowered until face
+ * neighbours are at most one apart; writes cluster[ne] and *dt0 (host).
+ * ESTATE before mesh and material; EINVAL for cfl <= 0 or max_clusters
+ * outside 1..8.
+ * dgd_step_lts: advances nmacro macro steps of dt0 2^(C-1) (C clusters), the
+ * receivers sampled at the end of each.  Synchronises (DGD_ENUMERIC like
+ * dgd_synchronize).  ESTATE without clusters or before mesh, material,
+ * params and state; EINVAL with point sources or the Picard predictor. */
+dgd_status dgd_set_clusters(dgd_handle* h, const int32_t* cluster, double dt0);
+dgd_status dgd_make_clusters(dgd_handle* h, double cfl, int max_clusters, int32_t* cluster,
+                             double* dt0);
+dgd_status dgd_step_lts(dgd_handle* h, int64_t nmacro);
+
 /* Point moment-tensor sources.  The paper drives its Gorkha runs with a
  * kinematic finite-fault source (Section 4.1) without printing how it enters
  * the discrete system; the reading used here is the equivalent body force

@@ -42,6 +42,9 @@ _SIGS = {
     "dgd_set_time": (ctypes.c_int, [H, ctypes.c_double]),
     "dgd_get_time": (ctypes.c_int, [H, c_dp]),
     "dgd_set_predictor": (ctypes.c_int, [H, ctypes.c_int, ctypes.c_int]),
+    "dgd_set_clusters": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_double]),
+    "dgd_make_clusters": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, c_dp]),
+    "dgd_step_lts": (ctypes.c_int, [H, ctypes.c_int64]),
     "dgd_set_point_sources": (ctypes.c_int, [H, ctypes.c_int, c_dp, c_dp, c_dp, c_dp, ctypes.c_int]),
     "dgd_set_receivers": (ctypes.c_int, [H, ctypes.c_int, c_dp]),
     "dgd_step": (ctypes.c_int, [H, ctypes.c_int64]),

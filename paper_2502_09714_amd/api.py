@@ -147,6 +147,26 @@ class Simulation:
         k = {"ck": 0, "picard": 1}[kind] if isinstance(kind, str) else int(kind)
         self._chk(self._L.dgd_set_predictor(self.h, k, int(iterations)))
 
+    def make_clusters(self, cfl=0.5, max_clusters=8):
+        """(cluster per element int32, dt0) proposed from the admissible steps."""
+        cl = np.zeros(self.ne, dtype=np.int32)
+        dt0 = ctypes.c_double()
+        self._chk(self._L.dgd_make_clusters(self.h, float(cfl), int(max_clusters),
+                                            cl.ctypes.data_as(ctypes.c_void_p), ctypes.byref(dt0)))
+        return cl, dt0.value
+
+    def set_clusters(self, cluster, dt0=0.0):
+        """Local time stepping clusters (None removes them)."""
+        if cluster is None:
+            self._chk(self._L.dgd_set_clusters(self.h, None, 0.0))
+            return
+        cl = np.ascontiguousarray(cluster, dtype=np.int32)
+        assert cl.shape == (self.ne,)
+        self._chk(self._L.dgd_set_clusters(self.h, cl.ctypes.data_as(ctypes.c_void_p), float(dt0)))
+
+    def step_lts(self, nmacro=1):
+        self._chk(self._L.dgd_step_lts(self.h, int(nmacro)))
+
     def set_point_sources(self, xyz, M6, t_onset, stf_param, stf_kind):
         xyz = _f64(xyz, (-1, 3))
         n = xyz.shape[0]

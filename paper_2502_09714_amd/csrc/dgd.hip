@@ -75,6 +75,17 @@ struct dgd_handle {
   DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Vd, wqd, Pwd, betad, KPpk;
   int predictor = 0;      // 0: linearised Cauchy-Kovalevskaya, 1: Picard iteration
   int picard_iters = 0;
+  // host copies of the connectivity (neighbour of every element face, face list)
+  std::vector<int> nbr_h, faces_h;
+  std::vector<double> fgeo_h;
+  // local time stepping: clusters, base step, per-cluster launch lists
+  int nclusters = 0;
+  double lts_dt0 = 0.0;
+  std::vector<signed char> cl_h;
+  DevBuf ecl, Dall, facc;
+  std::vector<DevBuf> lts_el, lts_tay, lts_fl, lts_acc;
+  std::vector<long long> n_el, n_tay, n_fl, n_acc;
+  double lts_tp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int kpl = 0;  // padded mode count of the time-point state layout
   double inv_wsum = 6.0, phi0_mean = 0.0;
   // mesh and material
@@ -121,10 +132,12 @@ struct dgd_handle {
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &gtr, &gmuf, &lzf, &gmu, &gcd, &adjW9,
                      &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea, &st9, &sta,
-                     &KPpk};
+                     &KPpk, &ecl, &Dall, &facc};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
+    for (auto* v : {&lts_el, &lts_tay, &lts_fl, &lts_acc})
+      for (DevBuf& b : *v) b.release();
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
       (void)hipEventDestroy(u.second.second);
@@ -380,6 +393,13 @@ StepArgs<P> make_args(dgd_handle* h) {
     a.gamma[z] = z < (int)h->ref.gamma.size() ? (T)h->ref.gamma[z] : T(0);
   }
   a.flag = (int*)h->flag.p;
+  a.elist = nullptr;
+  a.nlist = 0;
+  a.ecl = nullptr;
+  a.lts_c = -1;
+  a.facc = nullptr;
+  a.O9 = nullptr;
+  a.Oa = nullptr;
   return a;
 }
 
@@ -419,10 +439,12 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
     timed(h, 1, [&] {
       if (ivm)
         hipLaunchKernelGGL((k_face_flux<N, P, IvmLaw>), dim3((unsigned)(8 * fper)), block, 0,
-                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
+                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p,
+                           (const int*)nullptr);
       else
         hipLaunchKernelGGL((k_face_flux<N, P>), dim3((unsigned)(8 * fper)), block, 0,
-                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p);
+                           h->stream, a, (const int*)h->faces.p, h->nfaces, (T*)h->fflux.p,
+                           (const int*)nullptr);
     });
     timed(h, 8, [&] {
       hipLaunchKernelGGL((k_lift_update<N, P>), grid, block, 0, h->stream, a,
@@ -462,6 +484,109 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
   }
   return DGD_OK;
 }
+
+// ---------------------------------------------------------------- local time stepping
+// One step of cluster c over [t, t + dt0 2^c] (rate-2 clusters, the finer
+// cluster's two steps nested inside; see dgd_set_clusters).
+template <int N, int P>
+dgd_status lts_advance(dgd_handle* h, int c, double t) {
+  using T = typename Prec<P>::T;
+  const dim3 block(64);
+  auto grid_of = [](long long n) { return dim3((unsigned)(8 * ((n + 7) / 8))); };
+  const double dtc = h->lts_dt0 * (double)(1LL << c);
+  StepArgs<P> a = make_args<N, P>(h);
+  a.ecl = (const signed char*)h->ecl.p;
+  a.Dkeep = (T*)h->Dall.p;
+  a.Akeep = nullptr;
+  a.dt = dtc;
+  const bool ivm = h->law == 1;
+  if (h->n_el[c] > 0) {
+    a.elist = (const int*)h->lts_el[c].p;
+    a.nlist = h->n_el[c];
+    timed(h, 0, [&] {
+      if (ivm)
+        hipLaunchKernelGGL((k_predict<N, P, IvmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
+      else
+        hipLaunchKernelGGL((k_predict<N, P, CdmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
+    });
+    HIPCHK(h, hipGetLastError());
+  }
+  h->lts_tp[c] = t;
+  dgd_status s;
+  if (c > 0) {
+    if ((s = lts_advance<N, P>(h, c - 1, t)) || (s = lts_advance<N, P>(h, c - 1, t + 0.5 * dtc)))
+      return s;
+  }
+  if (h->n_el[c] == 0) return DGD_OK;
+  // states at this cluster's time points: its own and its coarser neighbours'
+  ClusterOffsets offs;
+  for (int k = 0; k < 8; ++k) offs.v[k] = k < h->nclusters ? t - h->lts_tp[k] : 0.0;
+  a.elist = (const int*)h->lts_tay[c].p;
+  a.nlist = h->n_tay[c];
+  timed(h, 0, [&] {
+    hipLaunchKernelGGL((k_taylor<N, P>), grid_of(a.nlist), block, 0, h->stream, a, offs);
+  });
+  // fluxes of the faces this cluster computes; integrals kept for the coarser side
+  if (h->n_fl[c] > 0) {
+    timed(h, 1, [&] {
+      if (ivm)
+        hipLaunchKernelGGL((k_face_flux<N, P, IvmLaw>), grid_of(h->n_fl[c]), block, 0, h->stream,
+                           a, (const int*)h->faces.p, h->n_fl[c], (T*)h->fflux.p,
+                           (const int*)h->lts_fl[c].p);
+      else
+        hipLaunchKernelGGL((k_face_flux<N, P, CdmLaw>), grid_of(h->n_fl[c]), block, 0, h->stream,
+                           a, (const int*)h->faces.p, h->n_fl[c], (T*)h->fflux.p,
+                           (const int*)h->lts_fl[c].p);
+    });
+  }
+  if (h->n_acc[c] > 0) {
+    const long long n = h->n_acc[c] * h->ref.Ns * 10;
+    hipLaunchKernelGGL((k_face_accumulate<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       h->stream, h->n_acc[c], (const int*)h->lts_acc[c].p, h->ref.Ns, dtc,
+                       (const T*)h->fflux.p, (T*)h->facc.p);
+  }
+  // volume and source terms, then the faces and the update in place
+  a.elist = (const int*)h->lts_el[c].p;
+  a.nlist = h->n_el[c];
+  timed(h, 9, [&] {
+    if (ivm)
+      hipLaunchKernelGGL((k_volume<N, P, IvmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
+    else
+      hipLaunchKernelGGL((k_volume<N, P, CdmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
+  });
+  a.lts_c = c;
+  a.facc = (T*)h->facc.p;
+  a.O9 = (T*)h->U9[h->cur].p;
+  a.Oa = (double*)h->Ua[h->cur].p;
+  timed(h, 8, [&] {
+    hipLaunchKernelGGL((k_lift_update<N, P>), grid_of(a.nlist), block, 0, h->stream, a,
+                       (const int*)h->fmap.p, (const T*)h->fflux.p);
+  });
+  HIPCHK(h, hipGetLastError());
+  return DGD_OK;
+}
+
+template <int N, int P> struct LtsFn {
+  static dgd_status run(dgd_handle* h, long long nmacro) {
+    using T = typename Prec<P>::T;
+    const double mdt = h->lts_dt0 * (double)(1LL << (h->nclusters - 1));
+    for (long long k = 0; k < nmacro; ++k) {
+      dgd_status s = lts_advance<N, P>(h, h->nclusters - 1, h->t);
+      if (s) return s;
+      h->t += mdt;
+      if (h->nrec > 0) {
+        double* out = (double*)h->seis.p + (size_t)h->nrec_steps * h->nrec * 3;
+        const int nth = h->nrec * 3;
+        hipLaunchKernelGGL((k_receivers<T>), dim3((nth + 63) / 64), dim3(64), 0, h->stream, h->nrec,
+                           h->ref.L, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                           (const T*)h->U9[h->cur].p, out);
+        h->nrec_steps += 1;
+      }
+      HIPCHK(h, hipGetLastError());
+    }
+    return DGD_OK;
+  }
+};
 
 // dispatch on (N, precision)
 template <template <int, int> class Fn, class... Args>
@@ -945,6 +1070,13 @@ dgd_status dgd_set_mesh(dgd_handle* h, int64_t nv, const double* xyz, int64_t ne
       (s = upload(h, h->faces, faces)) || (s = upload(h, h->fmap, fmap)))
     return s;
   h->nfaces = nfaces;
+  h->fgeo_h = fgeo;
+  h->nbr_h.assign((size_t)ne * 4, -1);
+  for (long long ef = 0; ef < ne * 4; ++ef)
+    if (conn_kind(conn[ef * 2 + 1]) == 0) h->nbr_h[ef] = conn[ef * 2];
+  h->faces_h.swap(faces);
+  h->nclusters = 0;
+  h->cl_h.clear();
   if ((s = alloc_state(h))) return s;
   h->have_mesh = true;
   h->have_mat = false;
@@ -1170,6 +1302,143 @@ dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations) {
   h->predictor = kind;
   h->picard_iters = iterations;
   return DGD_OK;
+}
+
+dgd_status dgd_set_clusters(dgd_handle* h, const int32_t* cluster, double dt0) {
+  if (!h) return DGD_EINVAL;
+  if (!h->have_mesh) return fail(h, DGD_ESTATE, "set_mesh first");
+  invalidate_tape(h);
+  for (auto* v : {&h->lts_el, &h->lts_tay, &h->lts_fl, &h->lts_acc})
+    for (DevBuf& b : *v) b.release();
+  h->nclusters = 0;
+  h->cl_h.clear();
+  if (!cluster) return DGD_OK;
+  if (!(dt0 > 0.0)) return fail(h, DGD_EINVAL, "dt0 > 0 needed");
+  const long long ne = h->ne;
+  std::vector<signed char> cl((size_t)ne);
+  int C = 0;
+  for (long long e = 0; e < ne; ++e) {
+    if (cluster[e] < 0 || cluster[e] > 7) return fail(h, DGD_EINVAL, "clusters 0..7");
+    cl[e] = (signed char)cluster[e];
+    C = std::max(C, (int)cluster[e] + 1);
+  }
+  for (long long ef = 0; ef < ne * 4; ++ef) {
+    const int nb = h->nbr_h[ef];
+    if (nb >= 0 && std::abs((int)cl[ef / 4] - (int)cl[nb]) > 1)
+      return fail(h, DGD_EINVAL, "face neighbours more than one cluster apart");
+  }
+  std::vector<std::vector<int>> el(C), tay(C), fl(C), acc(C);
+  for (long long e = 0; e < ne; ++e) el[cl[e]].push_back((int)e);
+  for (int c = 0; c < C; ++c) {
+    tay[c] = el[c];
+    if (c + 1 < C) {
+      std::vector<int> extra;
+      for (int e : el[c + 1])
+        for (int f = 0; f < 4; ++f) {
+          const int nb = h->nbr_h[(size_t)e * 4 + f];
+          if (nb >= 0 && cl[nb] == c) {
+            extra.push_back(e);
+            break;
+          }
+        }
+      tay[c].insert(tay[c].end(), extra.begin(), extra.end());
+      std::sort(tay[c].begin(), tay[c].end());
+    }
+  }
+  for (long long fid = 0; fid < h->nfaces; ++fid) {
+    const int ef = h->faces_h[fid * 2], of = h->faces_h[fid * 2 + 1];
+    const int c1 = cl[ef >> 2];
+    if (of < 0) {
+      fl[c1].push_back((int)fid);
+      continue;
+    }
+    const int c2 = cl[of >> 2], cm = std::min(c1, c2);
+    fl[cm].push_back((int)fid);
+    if (c1 != c2) acc[cm].push_back((int)fid);
+  }
+  h->lts_el.resize(C);
+  h->lts_tay.resize(C);
+  h->lts_fl.resize(C);
+  h->lts_acc.resize(C);
+  h->n_el.assign(C, 0);
+  h->n_tay.assign(C, 0);
+  h->n_fl.assign(C, 0);
+  h->n_acc.assign(C, 0);
+  dgd_status s;
+  for (int c = 0; c < C; ++c) {
+    if ((s = upload(h, h->lts_el[c], el[c])) || (s = upload(h, h->lts_tay[c], tay[c])) ||
+        (s = upload(h, h->lts_fl[c], fl[c])) || (s = upload(h, h->lts_acc[c], acc[c])))
+      return s;
+    h->n_el[c] = (long long)el[c].size();
+    h->n_tay[c] = (long long)tay[c].size();
+    h->n_fl[c] = (long long)fl[c].size();
+    h->n_acc[c] = (long long)acc[c].size();
+  }
+  if ((s = upload(h, h->ecl, cl))) return s;
+  h->cl_h.swap(cl);
+  h->nclusters = C;
+  h->lts_dt0 = dt0;
+  return DGD_OK;
+}
+
+dgd_status dgd_make_clusters(dgd_handle* h, double cfl, int max_clusters, int32_t* cluster,
+                             double* dt0) {
+  if (!h || !cluster || !dt0) return DGD_EINVAL;
+  if (!h->have_mesh || !h->have_mat) return fail(h, DGD_ESTATE, "mesh and material first");
+  if (!(cfl > 0.0) || max_clusters < 1 || max_clusters > 8)
+    return fail(h, DGD_EINVAL, "cfl > 0 and 1..8 clusters needed");
+  const long long ne = h->ne;
+  // admissible step of every element: cfl 2 r_in / ((2N+1) c_p), r_in = 3 V / A
+  std::vector<double> dte((size_t)ne);
+  double dmin = 1e300;
+  for (long long e = 0; e < ne; ++e) {
+    const double* m = &h->mat_h[e * 8];
+    const double cp = std::sqrt((m[1] + 2.0 * m[2]) / m[0]);   // intact moduli
+    // |S_f| / |J| are kept per face; V = |J| / 6, so r_in = 3 V / A = 1 / (2 sum |S_f|/|J|)
+    double sa = 0.0;
+    for (int f = 0; f < 4; ++f) sa += h->fgeo_h[(e * 4 + f) * 4 + 3];
+    const double r_in = 1.0 / (2.0 * sa);
+    dte[e] = cfl * 2.0 * r_in / ((2 * h->N + 1) * cp);
+    dmin = std::min(dmin, dte[e]);
+  }
+  std::vector<int> c((size_t)ne);
+  for (long long e = 0; e < ne; ++e)
+    c[e] = std::max(0, std::min(max_clusters - 1, (int)std::floor(std::log2(dte[e] / dmin) + 1e-12)));
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (long long e = 0; e < ne; ++e)
+      for (int f = 0; f < 4; ++f) {
+        const int nb = h->nbr_h[(size_t)e * 4 + f];
+        if (nb >= 0 && c[e] > c[nb] + 1) {
+          c[e] = c[nb] + 1;
+          changed = true;
+        }
+      }
+  }
+  for (long long e = 0; e < ne; ++e) cluster[e] = c[e];
+  *dt0 = dmin;
+  return DGD_OK;
+}
+
+dgd_status dgd_step_lts(dgd_handle* h, int64_t nmacro) {
+  if (!h) return DGD_EINVAL;
+  if (nmacro < 0) return fail(h, DGD_EINVAL, "negative step count");
+  if (h->nclusters < 1) return fail(h, DGD_ESTATE, "dgd_set_clusters first");
+  if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
+    return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
+  if (h->nsrc > 0) return fail(h, DGD_EINVAL, "point sources are not supported with clusters");
+  if (h->predictor != 0)
+    return fail(h, DGD_EINVAL, "local time stepping uses the Cauchy-Kovalevskaya predictor");
+  const size_t E = (size_t)h->ne;
+  dgd_status s;
+  if ((s = dalloc(h, h->Dall, E * h->N * h->kpl * 16 * h->tsize))) return s;
+  if (h->facc.n != (size_t)h->nfaces * h->ref.Ns * 10 * h->tsize) {
+    if ((s = dalloc(h, h->facc, (size_t)h->nfaces * h->ref.Ns * 10 * h->tsize))) return s;
+    HIPCHK(h, hipMemsetAsync(h->facc.p, 0, h->facc.n, h->stream));
+  }
+  if ((s = ensure_seis(h, nmacro))) return s;
+  if ((s = dispatch<LtsFn>(h, (long long)nmacro))) return s;
+  return dgd_synchronize(h);
 }
 
 dgd_status dgd_set_point_sources(dgd_handle* h, int n, const double* xyz, const double* M6,

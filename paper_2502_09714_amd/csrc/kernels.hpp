@@ -67,7 +67,29 @@ template <int P> struct StepArgs {
   T amax, smin, inv_wsum;
   T tau[8], gamma[8];
   int* flag;
+  // local time stepping: the elements a launch covers (null: all E), the
+  // cluster of every element, the cluster being corrected (-1: global step),
+  // flux integrals accumulated for the coarser side of cluster boundaries
+  // [face][Ns][10], and where the final update goes (null: W9 / Wa)
+  const int* elist;
+  long long nlist;
+  const signed char* ecl;
+  int lts_c;
+  T* facc;
+  T* O9;
+  double* Oa;
 };
+
+// element of this workgroup (-1: none), through the element list if any
+template <int P>
+__device__ inline long long elem_index(const StepArgs<P>& a) {
+  const long long n = a.elist ? a.nlist : a.E;
+  const long long per = (n + 7) / 8;
+  const long long b = blockIdx.x;
+  const long long i = (b % 8) * per + b / 8;
+  if (i >= n) return -1;
+  return a.elist ? (long long)a.elist[i] : i;
+}
 
 __device__ inline long long elem_of_block(long long E) {
   const long long per = (E + 7) / 8;
@@ -394,8 +416,8 @@ void k_predict(StepArgs<P> a) {
   T dreg[(N + 1) * DPL];
 
   const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  const long long e = elem_index(a);
+  if (e < 0) return;
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   predictor_stage<N, P, ND, REGS, true, LW>(a, e, S, m, lane, dreg);
   // D^i[idx] for idx = lane + 64 j
@@ -411,7 +433,7 @@ void k_predict(StepArgs<P> a) {
     for (int i = 1; i <= N; ++i)
 #pragma unroll
       for (int j = 0; j < DPL; ++j) De[(i - 1) * KPL * 16 + lane + 64 * j] = Dv(i, j);
-    if (lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
+    if (a.Akeep && lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
   }
   T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
 #pragma unroll
@@ -480,8 +502,8 @@ void k_predict_picard(StepArgs<P> a, PicardArgs<P> pa) {
   T* const sX = S.X;
 
   const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  const long long e = elem_index(a);
+  if (e < 0) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   if (lane < 9) S.J[lane] = (T)a.geo[e * 16 + lane];
@@ -619,8 +641,8 @@ void k_volume(StepArgs<P> a) {
   T* const sR = S.R_;
 
   const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  const long long e = elem_index(a);
+  if (e < 0) return;
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
   T Ji[9];
@@ -740,7 +762,8 @@ template <int N, int P> struct FaceWaves {
 
 template <int N, int P, class LW = CdmLaw>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FaceWaves<N, P>::value)))
-void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux) {
+void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Prec<P>::T* fflux,
+                 const int* flist) {
   using PR = Prec<P>;
   using T = typename PR::T;
   using Acc = typename PR::Acc;
@@ -755,8 +778,9 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   __shared__ T sTp[Nt * TS];
 
   const int lane = threadIdx.x;
-  const long long fid = elem_of_block(nfaces);
+  long long fid = elem_of_block(nfaces);
   if (fid >= nfaces) return;
+  if (flist) fid = flist[fid];
   const int ef = faces[fid * 2], of = faces[fid * 2 + 1];
   const long long e = ef >> 2;
   const int f = ef & 3;
@@ -843,22 +867,33 @@ __global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fm
   constexpr int WPL = (9 * L + 63) / 64;     // partial-update values per lane
 
   const int lane = threadIdx.x;
-  const long long e = elem_of_block(a.E);
-  if (e >= a.E) return;
+  const long long e = elem_index(a);
+  if (e < 0) return;
   // every HBM load is issued before the first use: the four faces' fluxes
-  // (gathered by face) and the partial update
+  // (gathered by face) and the partial update.  Under local time stepping a
+  // face shared with the finer cluster brings the flux integral that cluster
+  // accumulated over its two steps (already scaled by its step), and clears it.
   T fv[4][FPL], sc[4];
   int sp[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     const int fm = fmap[e * 4 + f];
     sp[f] = conn_perm(a.conn[(e * 4 + f) * 2 + 1]);
-    sc[f] = (T)((fm & 1 ? -1.0 : 1.0) * a.fgeo[(e * 4 + f) * 4 + 3] * a.dt);
-    const T* fl = fflux + (size_t)(fm >> 1) * Ns * 10;
+    const int nb = a.conn[(e * 4 + f) * 2];
+    const bool fine = a.lts_c > 0 && nb >= 0 && a.ecl[nb] == a.lts_c - 1;
+    sc[f] = (T)((fm & 1 ? -1.0 : 1.0) * a.fgeo[(e * 4 + f) * 4 + 3] * (fine ? 1.0 : a.dt));
+    T* fl = (fine ? a.facc : (T*)fflux) + (size_t)(fm >> 1) * Ns * 10;
 #pragma unroll
     for (int j = 0; j < FPL; ++j) {
       const int idx = lane + 64 * j;
       fv[f][j] = idx < Ns * 10 ? fl[idx] : T(0);
+    }
+    if (fine) {
+#pragma unroll
+      for (int j = 0; j < FPL; ++j) {
+        const int idx = lane + 64 * j;
+        if (idx < Ns * 10) fl[idx] = T(0);
+      }
     }
   }
   T* W9 = a.W9 + e * 9 * L;
@@ -890,6 +925,8 @@ __global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fm
   store_C<P, MT>(Fc, sF, L, T(1), lane);
   __syncthreads();
   bool bad = false;
+  T* O9 = (a.O9 ? a.O9 : a.W9) + e * 9 * L;
+  double* Oa = a.Oa ? a.Oa : a.Wa;
 #pragma unroll
   for (int j = 0; j < WPL; ++j) {
     const int idx = lane + 64 * j;
@@ -897,15 +934,75 @@ __global__ __launch_bounds__(64) void k_lift_update(StepArgs<P> a, const int* fm
       const int p = idx / L, l = idx - p * L;
       const T v = wv[j] - sF[l * R + p];
       bad |= !isfinite(v);
-      W9[idx] = v;
+      O9[idx] = v;
     }
   }
   if (lane < L) {
     const double v = wa - (double)sF[lane * R + 9];
     bad |= !isfinite(v);
-    a.Wa[e * L + lane] = v;
+    Oa[e * L + lane] = v;
   }
   if (bad) a.flag[0] = 1;
+}
+
+// Local time stepping: the state of each listed element at the time points
+// t_pred + off + tau_z dt of the cluster being corrected, from its kept
+// prediction (D^0 = its state, D^1..D^N kept by k_predict), written to Uz in
+// the [l][16] layout; off is the time since the element's own prediction.
+// The Taylor sum is formed exactly as in k_predict.
+struct ClusterOffsets { double v[8]; };   // time since each cluster's prediction
+
+template <int N, int P>
+__global__ __launch_bounds__(64) void k_taylor(StepArgs<P> a, ClusterOffsets offs) {
+  using T = typename Prec<P>::T;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Nt = DM::Nt;
+  constexpr int KPL = round_up(L, Prec<P>::KS), DPL = KPL * 16 / 64;
+  const int lane = threadIdx.x;
+  const long long e = elem_index(a);
+  if (e < 0) return;
+  const double off = offs.v[a.ecl[e]];
+  const T* U9 = a.U9 + e * 9 * L;
+  const T* De = a.Dkeep + (size_t)e * N * KPL * 16;
+  T d[N + 1][DPL];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+    d[0][j] = (l < L && p < 10) ? (p < 9 ? U9[p * L + l] : (T)a.Ua[e * L + l]) : T(0);
+  }
+#pragma unroll
+  for (int i = 1; i <= N; ++i)
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) d[i][j] = De[(i - 1) * KPL * 16 + lane + 64 * j];
+  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+#pragma unroll
+  for (int z = 0; z < Nt; ++z) {
+    T cz[N + 1];
+    cz[0] = T(1);
+    const T h = a.tau[z] * (T)a.dt + (T)off;   // as k_predict's when off = 0
+#pragma unroll
+    for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i <= N; ++i) v += cz[i] * d[i][j];
+      Uzo[z * KPL * 16 + lane + 64 * j] = v;
+    }
+  }
+}
+
+// Local time stepping: faces between the cluster being corrected and the next
+// coarser one keep the time integral of their flux for the coarser side:
+// acc += dt * flux over the listed faces.
+template <class T>
+__global__ void k_face_accumulate(long long nlist, const int* flist, int Ns, double dt,
+                                  const T* fflux, T* facc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlist * Ns * 10) return;
+  const long long f = flist[i / (Ns * 10)];
+  const long long k = f * Ns * 10 + i % (Ns * 10);
+  facc[k] = (T)((double)facc[k] + dt * (double)fflux[k]);
 }
 
 // ---- point sources, receivers, projection, diagnostics ------------------------

@@ -6,8 +6,13 @@ from the same run with mu0 perturbed by 5 % and C_d by 20 % per element (seeded)
 
 The FP32 and FP64 adjoint gradients with respect to per-element mu0 and C_d
 are checked against central finite differences of the FP64 forward run
-(relative step 1e-4) on 10 seeded elements drawn among those the misfit is
-sensitive to (|dJ/dp| at least 1e-3 of its maximum): relative L2 1e-4.
+(relative step 1e-4) on elements chosen without looking at the gradient: 20
+drawn at random per parameter, plus the element holding the source, one
+under a receiver (a free-surface face), one on an absorbing face and one on
+an absorbing edge.  Bar per element: |g - fd| <= 1e-4 |fd| + a max|fd|, with
+a = 1e-6 for the FP64 adjoint and 1e-5 for the FP32 one (the absolute part
+covers elements the misfit hardly sees, whose difference quotient carries the
+forward run's rounding, and the FP32 adjoint's own rounding).
 """
 import numpy as np
 import pytest
@@ -60,14 +65,40 @@ def _misfit(s64, U0, obs, mat):
     return 0.5 * float(((seis - obs) ** 2).sum())
 
 
+def _locate(w, x):
+    """Element of the structured mesh containing point x (its cube, then the
+    tetrahedron whose barycentric coordinates are all non-negative)."""
+    m = w.mesh
+    n, h = m["n"], m["edge"]
+    o = m["xyz"].min(axis=0)
+    ijk = np.minimum(((np.asarray(x) - o) // h).astype(int), n - 1)
+    cube = ijk[0] + n * (ijk[1] + n * ijk[2])
+    for e in range(6 * cube, 6 * cube + 6):
+        X = m["xyz"][m["tets"][e]]
+        lam = np.linalg.solve((X[1:] - X[0]).T, np.asarray(x) - X[0])
+        if lam.min() >= -1e-12 and lam.sum() <= 1 + 1e-12:
+            return e
+    raise AssertionError("point outside its cube")
+
+
+def _chosen_elements(w, seed):
+    tag = w.mesh["face_tag"]
+    rng = np.random.default_rng(seed)
+    picks = [int(e) for e in rng.choice(w.ne, 20, replace=False)]
+    picks.append(_locate(w, w.sources["xyz"][0]))                   # source host
+    picks.append(_locate(w, w.receivers[5]))                        # under a receiver
+    picks.append(int(np.nonzero((tag == 2).sum(1) == 1)[0][w.ne // 7 % 100]))   # absorbing face
+    picks.append(int(np.nonzero((tag == 2).sum(1) >= 2)[0][0]))     # absorbing edge
+    return list(dict.fromkeys(picks))
+
+
 @pytest.mark.parametrize("which", ["mu0", "Cd"])
 def test_c4_gradient_central_differences(c4, which):
     w, s64, U0, obs, base, grads = c4
     k = 0 if which == "mu0" else 1
     g64, g32 = grads["fp64"][k], grads["fp32"][k]
     assert np.isfinite(g64).all() and np.isfinite(g32).all()
-    cand = np.nonzero(np.abs(g64) >= 1e-3 * np.abs(g64).max())[0]
-    idx = np.random.default_rng(17 + k).choice(cand, 10, replace=False)
+    idx = _chosen_elements(w, 17 + k)
     fd = []
     for e in idx:
         h = 1e-4 * base[which][e]
@@ -78,10 +109,10 @@ def test_c4_gradient_central_differences(c4, which):
         jm = _misfit(s64, U0, obs, mp)
         fd.append((jp - jm) / (2 * h))
     fd = np.asarray(fd)
-    r64 = np.linalg.norm(g64[idx] - fd) / np.linalg.norm(fd)
-    r32 = np.linalg.norm(g32[idx] - fd) / np.linalg.norm(fd)
-    assert r64 < 1e-4, (r64, g64[idx], fd)
-    assert r32 < 1e-4, (r32, g32[idx], fd)
+    assert np.abs(fd).max() > 0
+    for g, name, floor in ((g64[idx], "fp64", 1e-6), (g32[idx], "fp32", 1e-5)):
+        bad = np.abs(g - fd) > 1e-4 * np.abs(fd) + floor * np.abs(fd).max()
+        assert not bad.any(), (which, name, np.asarray(idx)[bad], g[bad], fd[bad])
 
 
 def test_c4_fp32_adjoint_matches_fp64(c4):
