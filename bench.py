@@ -252,6 +252,62 @@ def fd_check(w, steps, grads, nelem, seed=31):
     return rows
 
 
+def run_lts(w, prec, nmacro, gts_ms_per_step, max_clusters=8):
+    """Clustered local time stepping on the step workload: clusters proposed
+    from the per-element admissible steps, nmacro macro steps timed."""
+    import numpy as np
+    import torch
+    from paper_2502_09714_amd.api import from_workload
+    sim = from_workload(w, prec)
+    sim.set_check_interval(1 << 40)
+    cl, dt0 = sim.make_clusters(0.5, max_clusters)
+    sim.set_clusters(cl, dt0)
+    C = int(cl.max()) + 1
+    sim.step_lts(1)                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_lts(nmacro)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    sim.close()
+    counts = np.bincount(cl, minlength=C)
+    mdt = dt0 * 2 ** (C - 1)
+    L = w.L
+    # element updates per macro step: cluster c steps 2^(C-1-c) times
+    upd = sum(int(counts[c]) * 2 ** (C - 1 - c) for c in range(C))
+    gts_steps = mdt / w.dt
+    return {"clusters": [int(x) for x in counts], "dt0": dt0, "macro_dt": mdt,
+            "macro_steps": nmacro, "ms_per_macro_step": 1e3 * secs / nmacro,
+            "dof_updates_per_s": upd * L * 10 * nmacro / secs,
+            "simulated_s_per_wall_s": mdt * nmacro / secs,
+            "global_step_simulated_s_per_wall_s": w.dt / (gts_ms_per_step * 1e-3),
+            "speedup_vs_global_step": (gts_steps * gts_ms_per_step) / (1e3 * secs / nmacro),
+            "work_ratio": upd / (w.ne * gts_steps)}
+
+
+def run_picard(w, prec, steps, warmup):
+    """Step time with the Picard-iteration predictor (N + 1 sweeps)."""
+    import torch
+    from paper_2502_09714_amd.api import from_workload
+    sim = from_workload(w, prec)
+    sim.set_predictor("picard")
+    sim.set_check_interval(1 << 40)
+    sim.step(warmup)
+    sim.synchronize()
+    sim.get_kernel_times()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    secs = time.perf_counter() - t0
+    ms, _ = sim.get_kernel_times()
+    sim.close()
+    return {"iterations": w.N + 1, "ms_per_step": 1e3 * secs / steps,
+            "predictor_ms_per_step": float(ms[0]) / steps,
+            "dof_updates_per_s": w.ne * w.L * 10 * steps / secs}
+
+
 def rel_l2(a, b):
     import numpy as np
     out = {}
@@ -406,7 +462,7 @@ def main():
     ap.add_argument("--error-precisions", default="fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=3)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--adjoint-precisions", default="",
                     help="precisions whose checkpointed adjoint is timed on the step workload "
                          "('' for none)")
@@ -417,6 +473,10 @@ def main():
                     help="central differences on this many elements for the last adjoint run")
     ap.add_argument("--ivm-precisions", default="fp32",
                     help="precisions of the IVM-rheology step timing ('' for none)")
+    ap.add_argument("--lts-macro-steps", type=int, default=3,
+                    help="macro steps of the local-time-stepping timing (0 for none)")
+    ap.add_argument("--picard-steps", type=int, default=3,
+                    help="steps of the Picard-predictor timing (0 for none)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -494,6 +554,12 @@ def main():
         for p in precs:
             if p != "fp64":
                 line[f"speedup_{p}_vs_fp64"] = rate(p) / rate("fp64")
+    if args.lts_macro_steps > 0:
+        line["lts"] = run_lts(w, main_prec, args.lts_macro_steps, res[main_prec]["ms_per_step"])
+        print(f"lts: {line['lts']}", file=sys.stderr, flush=True)
+    if args.picard_steps > 0:
+        line["picard"] = run_picard(w, main_prec, args.picard_steps, 1)
+        print(f"picard: {line['picard']}", file=sys.stderr, flush=True)
     ivm_precs = [q.strip() for q in args.ivm_precisions.split(",") if q.strip()]
     if ivm_precs:
         # the same workload with the internal-variable rheology (Eq. ivm-model);

@@ -221,7 +221,8 @@ dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations);
  * steps; volume and source terms and the update are those of the global
  * step.  Every face flux is computed once, by the finer side, so the wave
  * quantities are conserved across cluster boundaries; one cluster is the
- * global step.
+ * global step.  A point source adds its time integral over its element's
+ * step after that element's update.
  * dgd_set_clusters: cluster per element (host, ne, copied) and dt0 (> 0);
  * NULL removes the clusters.  ESTATE before the mesh.  Drops a checkpointed
  * run.
@@ -234,7 +235,7 @@ dgd_status dgd_set_predictor(dgd_handle* h, int kind, int iterations);
  * dgd_step_lts: advances nmacro macro steps of dt0 2^(C-1) (C clusters), the
  * receivers sampled at the end of each.  Synchronises (DGD_ENUMERIC like
  * dgd_synchronize).  ESTATE without clusters or before mesh, material,
- * params and state; EINVAL with point sources or the Picard predictor. */
+ * params and state; EINVAL with the Picard predictor. */
 dgd_status dgd_set_clusters(dgd_handle* h, const int32_t* cluster, double dt0);
 dgd_status dgd_make_clusters(dgd_handle* h, double cfl, int max_clusters, int32_t* cluster,
                              double* dt0);

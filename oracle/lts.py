@@ -28,6 +28,8 @@ the clustered ADER-DG schemes the paper cites for the linear case):
   Each face flux is computed once, at the time points of the finer side, and
   used by both sides, so the wave quantities stay conserved across cluster
   boundaries.  With one cluster the scheme is the global step.
+* A point source adds its exact time integral over its element's own step
+  after that element's update, as in the global step.
 """
 import numpy as np
 import torch
@@ -64,8 +66,11 @@ class LtsSolver:
     """Clustered local time stepping around an OracleSolver S (which supplies
     the predictor, the volume/source terms, the face fluxes and the lift)."""
 
-    def __init__(self, S, clusters, dt0):
+    def __init__(self, S, clusters, dt0, sources=None):
         self.S = S
+        # point sources (oracle.sources.PointSources): each one's time integral
+        # over its element's own step is added after that element's update
+        self.sources = sources
         self.cl = np.asarray(clusters, dtype=np.int64)
         self.C = int(self.cl.max()) + 1
         self.dt0 = float(dt0)
@@ -146,3 +151,6 @@ class LtsSolver:
         upd = torch.einsum("kl,mlp->mkp", ref.Minv, vol + src - face)
         idx = torch.as_tensor(np.nonzero(sel)[0])
         self.U[idx] = self.U[idx] + upd[idx]
+        if self.sources is not None:
+            dU = self.sources.increment(t, t + dtc)
+            self.U[idx] = self.U[idx] + dU[idx]

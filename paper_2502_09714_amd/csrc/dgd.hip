@@ -73,6 +73,7 @@ struct dgd_handle {
   size_t tsize = 8;  // bytes of the working type
   // reference data on the device
   DevBuf Vpk, Kpk, Spk, Fpk, Lpk, Ppk, Vd, wqd, Pwd, betad, KPpk;
+  bool vol3 = false;      // volume terms three elements per wavefront
   int predictor = 0;      // 0: linearised Cauchy-Kovalevskaya, 1: Picard iteration
   int picard_iters = 0;
   // host copies of the connectivity (neighbour of every element face, face list)
@@ -403,6 +404,27 @@ StepArgs<P> make_args(dgd_handle* h) {
   return a;
 }
 
+// volume and source terms of the listed elements (all without a list): three
+// elements per wavefront where that layout is used, else one
+template <int N, int P>
+void launch_volume(dgd_handle* h, const StepArgs<P>& a, bool ivm) {
+  const long long n = a.elist ? a.nlist : a.E;
+  if (h->vol3) {
+    const long long ng = (n + 2) / 3;
+    const dim3 grid((unsigned)(8 * ((ng + 7) / 8)));
+    if (ivm)
+      hipLaunchKernelGGL((k_volume3<N, P, IvmLaw>), grid, dim3(64), 0, h->stream, a);
+    else
+      hipLaunchKernelGGL((k_volume3<N, P, CdmLaw>), grid, dim3(64), 0, h->stream, a);
+  } else {
+    const dim3 grid((unsigned)(8 * ((n + 7) / 8)));
+    if (ivm)
+      hipLaunchKernelGGL((k_volume<N, P, IvmLaw>), grid, dim3(64), 0, h->stream, a);
+    else
+      hipLaunchKernelGGL((k_volume<N, P, CdmLaw>), grid, dim3(64), 0, h->stream, a);
+  }
+}
+
 template <int N, int P>
 dgd_status step_impl(dgd_handle* h, long long nsteps) {
   using T = typename Prec<P>::T;
@@ -429,12 +451,7 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
         hipLaunchKernelGGL((k_predict<N, P, CdmLaw>), grid, block, 0, h->stream, a);
       }
     });
-    timed(h, 9, [&] {
-      if (ivm)
-        hipLaunchKernelGGL((k_volume<N, P, IvmLaw>), grid, block, 0, h->stream, a);
-      else
-        hipLaunchKernelGGL((k_volume<N, P, CdmLaw>), grid, block, 0, h->stream, a);
-    });
+    timed(h, 9, [&] { launch_volume<N, P>(h, a, ivm); });
     const long long fper = (h->nfaces + 7) / 8;
     timed(h, 1, [&] {
       if (ivm)
@@ -463,6 +480,8 @@ dgd_status step_impl(dgd_handle* h, long long nsteps) {
       s.kind = h->srckind;
       s.t0 = h->t;
       s.t1 = h->t + h->dt;
+      s.ecl = nullptr;
+      s.only_cluster = -1;
       timed(h, 2, [&] {
         hipLaunchKernelGGL((k_sources<T>), dim3(1), dim3(3 * h->ref.L), 0, h->stream, s,
                            (T*)h->U9[1 - h->cur].p);
@@ -548,12 +567,7 @@ dgd_status lts_advance(dgd_handle* h, int c, double t) {
   // volume and source terms, then the faces and the update in place
   a.elist = (const int*)h->lts_el[c].p;
   a.nlist = h->n_el[c];
-  timed(h, 9, [&] {
-    if (ivm)
-      hipLaunchKernelGGL((k_volume<N, P, IvmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
-    else
-      hipLaunchKernelGGL((k_volume<N, P, CdmLaw>), grid_of(a.nlist), block, 0, h->stream, a);
-  });
+  timed(h, 9, [&] { launch_volume<N, P>(h, a, ivm); });
   a.lts_c = c;
   a.facc = (T*)h->facc.p;
   a.O9 = (T*)h->U9[h->cur].p;
@@ -562,6 +576,27 @@ dgd_status lts_advance(dgd_handle* h, int c, double t) {
     hipLaunchKernelGGL((k_lift_update<N, P>), grid_of(a.nlist), block, 0, h->stream, a,
                        (const int*)h->fmap.p, (const T*)h->fflux.p);
   });
+  if (h->nsrc > 0) {
+    // the point sources of this cluster's elements, over its step
+    SrcArgs sa;
+    sa.nsrc = h->nsrc;
+    sa.L = h->ref.L;
+    sa.elem = (const long long*)h->s_elem.p;
+    sa.M6 = (const double*)h->s_M6.p;
+    sa.dphi = (const double*)h->s_dphi.p;
+    sa.onset = (const double*)h->s_onset.p;
+    sa.param = (const double*)h->s_param.p;
+    sa.rhoJ = (const double*)h->s_rhoJ.p;
+    sa.kind = h->srckind;
+    sa.t0 = t;
+    sa.t1 = t + dtc;
+    sa.ecl = (const signed char*)h->ecl.p;
+    sa.only_cluster = c;
+    timed(h, 2, [&] {
+      hipLaunchKernelGGL((k_sources<T>), dim3(1), dim3(3 * h->ref.L), 0, h->stream, sa,
+                         (T*)h->U9[h->cur].p);
+    });
+  }
   HIPCHK(h, hipGetLastError());
   return DGD_OK;
 }
@@ -893,6 +928,10 @@ dgd_status dgd_create(int N, int precision, void* hip_stream, dgd_handle** out) 
   h->prec = precision;
   h->stream = (hipStream_t)hip_stream;
   h->tsize = precision == DGD_FP64 ? 8 : 4;
+  {
+    const char* v = getenv("DGD_VOLUME_KERNEL");
+    h->vol3 = v && v[0] == '3';
+  }
   if (hipGetDevice(&h->device) != hipSuccess ||
       scratch_address(h->device, &h->noalloc_part) != hipSuccess) {
     delete h;
@@ -1426,7 +1465,6 @@ dgd_status dgd_step_lts(dgd_handle* h, int64_t nmacro) {
   if (h->nclusters < 1) return fail(h, DGD_ESTATE, "dgd_set_clusters first");
   if (!h->have_mesh || !h->have_mat || !h->have_params || !h->have_state)
     return fail(h, DGD_ESTATE, "mesh, material, params and state are needed before step");
-  if (h->nsrc > 0) return fail(h, DGD_EINVAL, "point sources are not supported with clusters");
   if (h->predictor != 0)
     return fail(h, DGD_EINVAL, "local time stepping uses the Cauchy-Kovalevskaya predictor");
   const size_t E = (size_t)h->ne;

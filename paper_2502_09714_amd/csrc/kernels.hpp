@@ -752,6 +752,194 @@ void k_volume(StepArgs<P> a) {
 }
 
 
+// ---- volume and source terms, three elements per wavefront -----------------------
+// The same computation as k_volume with the 10 quantities of three elements
+// side by side in the columns of every reference-matrix contraction (column
+// 10 j + p for element j, quantity p; 30 of 32 columns used): each A fragment
+// feeds two matrix-core products for three elements instead of one product
+// (10 of 16 columns) for one.
+template <int N, int P> struct Vol3LDS {
+  using T = typename Prec<P>::T;
+  static constexpr int RS = 33;                     // 32 columns, odd stride
+  static constexpr int KPL = round_up(Dims<N>::L, Prec<P>::KS);
+  static constexpr int XR = 64 > KPL ? 64 : KPL;
+  T X[XR * RS];                                     // point values / integrands of a chunk
+  T W[KPL * RS];                                    // time-point states of the three elements
+  T J[3][9];
+  T M[3][8];                                        // materials of the three elements
+};
+
+#ifndef DGD_VOL3_WAVES
+#define DGD_VOL3_WAVES 2
+#endif
+
+template <int N, int P, class LW = CdmLaw>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DGD_VOL3_WAVES)))
+void k_volume3(StepArgs<P> a) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  constexpr int PA_ = Accurate<P>::value;
+  using PA = Prec<PA_>;
+  using DM = Dims<N>;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
+  constexpr int KSQ = 64 / KS, KSQA = 64 / PA::KS;
+  constexpr int DPL = KPL * 16 / 64;
+  using SL = Vol3LDS<N, P>;
+  constexpr int RS = SL::RS;
+  __shared__ SL S;
+  T* const sX = S.X;
+  T* const sW = S.W;
+
+  const int lane = threadIdx.x;
+  const long long n = a.elist ? a.nlist : a.E;
+  const long long ng = (n + 2) / 3;
+  const long long per = (ng + 7) / 8;
+  const long long g = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= ng) return;
+  long long el[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const long long i = 3 * g + j;
+    el[j] = i < n ? (a.elist ? (long long)a.elist[i] : i) : -1;
+  }
+  const Law<T> law{a.amax, a.smin};
+  if (lane < 24) {
+    const long long ej = el[lane / 8] >= 0 ? el[lane / 8] : el[0];
+    S.M[lane / 8][lane % 8] = (T)a.mat[ej * 8 + lane % 8];
+  }
+  auto mat_of = [&](int j) {
+    MatP<T> mm;
+    mm.rho = S.M[j][0];
+    mm.lam = S.M[j][1];
+    mm.mu = S.M[j][2];
+    mm.gr = S.M[j][3];
+    mm.xi0 = S.M[j][4];
+    mm.cd = S.M[j][5];
+    return mm;
+  };
+  if (lane < 27) {
+    const long long ej = el[lane / 9];
+    S.J[lane / 9][lane % 9] = ej >= 0 ? (T)a.geo[ej * 16 + lane % 9] : T(0);
+  }
+  for (int i = lane; i < KPL * RS; i += 64) sW[i] = T(0);
+
+
+  T vs[NCH][3][3], ss[NCH][3][6], sacc[NCH][3];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      sacc[c][j] = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vs[c][j][k] = T(0);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) ss[c][j][k] = T(0);
+    }
+  for (int z = 0; z < Nt; ++z) {
+    const T gz = a.gamma[z];
+    __syncthreads();
+    // the three elements' time-point states, quantities side by side
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T* Uz = a.Uz + (size_t)(el[j] >= 0 ? el[j] : el[0]) * Nt * KPL * 16 + z * KPL * 16;
+#pragma unroll
+      for (int q = 0; q < DPL; ++q) {
+        const int idx = lane + 64 * q, l = idx >> 4, p = idx & 15;
+        if (p < 10) sW[l * RS + 10 * j + p] = el[j] >= 0 ? Uz[idx] : T(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      Acc C[4][2];
+      zero_C2<P, 4>(C);
+      wave_gemm2<P, 4, KSL, RS>(a.Vpk + (size_t)c * 4 * KSL * 64, sW, C, lane);
+      store_C2<P, 4, RS>(C, sX, 64, T(1), lane);
+      __syncthreads();
+      if (64 * c + lane < Q) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          T u[10];
+#pragma unroll
+          for (int k = 0; k < 10; ++k) u[k] = sX[lane * RS + 10 * j + k];
+          T sig[6];
+          sacc[c][j] += gz * LW::stress_rate(u, mat_of(j), law, sig);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) ss[c][j][k] += gz * sig[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) vs[c][j][k] += gz * u[6 + k];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // volume contraction sum_e Sw^e G^e and the damage-source projection
+  Acc Vc[MT][2];
+  zero_C2<P, MT>(Vc);
+#pragma unroll 1
+  for (int ee = 0; ee < 3; ++ee) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T ir = T(1) / S.M[j][0];
+        T Jr[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Jr[d] = S.J[j][ee * 3 + d];
+        T* row = sX + lane * RS + 10 * j;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+          const int ii = kVI[p], jj = kVJ[p];
+          row[p] = T(-0.5) * (Jr[jj] * vs[c][j][ii] + Jr[ii] * vs[c][j][jj]);
+        }
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          T t = T(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) t += Jr[d] * ss[c][j][sym_idx(ii, d)];
+          row[6 + ii] = -ir * t;
+        }
+        row[9] = T(0);
+      }
+      sX[lane * RS + 30] = T(0);
+      sX[lane * RS + 31] = T(0);
+      __syncthreads();
+      wave_gemm2<P, MT, KSQ, RS>(a.Spk + (size_t)(ee * NCH + c) * MT * KSQ * 64, sX, Vc, lane);
+      __syncthreads();
+    }
+  }
+  // damage source: the rate integrals in the damage columns 10 j + 9
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+    for (int k = 0; k < 32; ++k) sX[lane * RS + k] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sX[lane * RS + 10 * j + 9] = sacc[c][j];
+    __syncthreads();
+    wave_gemm2<PA_, MT, KSQA, RS>(a.Ppk + (size_t)c * MT * KSQA * 64, sX, Vc, lane);
+    __syncthreads();
+  }
+  store_C2<P, MT, RS>(Vc, sX, L, (T)a.dt, lane);
+  __syncthreads();
+  // U^n + volume for the nine wave quantities; the damage increment joins the
+  // FP64 damage plane
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (el[j] < 0) continue;
+    const long long e = el[j];
+    const T* U9 = a.U9 + e * 9 * L;
+    T* W9 = a.W9 + e * 9 * L;
+    for (int idx = lane; idx < 9 * L; idx += 64) {
+      const int p = idx / L, l = idx - p * L;
+      W9[idx] = U9[idx] + sX[l * RS + 10 * j + p];
+    }
+    if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sX[lane * RS + 10 * j + 9];
+  }
+}
+
 // One wavefront per face (interior faces once, boundary faces once): traces of
 // both sides at the shared face points for every time point, LLF (or
 // boundary) flux with the normal of the face's first element, time quadrature.
@@ -1025,6 +1213,8 @@ struct SrcArgs {
   const double* rhoJ;      // [nsrc]  rho |J| of the host element
   int kind;
   double t0, t1;
+  const signed char* ecl;  // cluster of every element, with only_cluster >= 0
+  int only_cluster;        // -1: every source; else those in elements of this cluster
 };
 
 template <class T>
@@ -1033,6 +1223,7 @@ __global__ void k_sources(SrcArgs s, T* U9) {
   if (idx >= 3 * s.L) return;
   const int i = idx / s.L, l = idx % s.L;
   for (int k = 0; k < s.nsrc; ++k) {
+    if (s.only_cluster >= 0 && s.ecl[s.elem[k]] != s.only_cluster) continue;
     const double dG = stf_G(s.kind, s.t1 - s.onset[k], s.param[k]) -
                       stf_G(s.kind, s.t0 - s.onset[k], s.param[k]);
     const double fac = dG / s.rhoJ[k];

@@ -175,6 +175,51 @@ __device__ inline void wave_gemm_tiles(const typename Prec<P>::AF* __restrict__ 
                      C[t]);
 }
 
+// C += A x B for a B of 32 columns (two 16-column tiles, row stride RS): each
+// A fragment feeds two matrix-core products.
+template <int P, int MT, int KSTEPS, int RS>
+__device__ inline void wave_gemm2(const typename Prec<P>::AF* __restrict__ Apk,
+                                  const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT][2],
+                                  int lane) {
+  using PR = Prec<P>;
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    const typename PR::AF b0 = PR::template loadB<RS>(B, s, lane);
+    const typename PR::AF b1 = PR::template loadB<RS>(B + 16, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const typename PR::AF av = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
+      C[t][0] = PR::mma(av, b0, C[t][0]);
+      C[t][1] = PR::mma(av, b1, C[t][1]);
+    }
+  }
+}
+
+template <int P, int MT>
+__device__ inline void zero_C2(typename Prec<P>::Acc (&C)[MT][2]) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) C[t][h][i] = 0;
+}
+
+// Store 32-column C tiles to a [rows][RS] matrix, rows >= rmax dropped, times scale.
+template <int P, int MT, int RS>
+__device__ inline void store_C2(const typename Prec<P>::Acc (&C)[MT][2], typename Prec<P>::T* dst,
+                                int rmax, typename Prec<P>::T scale, int lane) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * t + Prec<P>::crow(lane, i);
+        if (r < rmax) dst[r * RS + 16 * h + (lane & 15)] = scale * C[t][h][i];
+      }
+}
+
 // C += A x B with B[k][n] = (n == 9) ? v[k] : 0 (a vector placed in the damage column)
 template <int P, int MT, int KSTEPS>
 __device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ Apk,

@@ -9,7 +9,9 @@ dgd_make_clusters, dgd_step_lts) against the oracle's (oracle/lts.py).
   clusters from the wave speeds, and a bounded mesh with damage growth and a
   clustered half; FP64 1e-10, FP32 1e-5, BF16 3e-3.
 * The wave quantities are conserved across cluster boundaries on the device.
-* Refusals: neighbours two clusters apart, point sources, the Picard predictor.
+* A point source (the c4 double couple, Ricker moment rate) in a clustered
+  mesh, with receivers: state and seismograms against the oracle.
+* Refusals: neighbours two clusters apart, the Picard predictor.
 """
 import numpy as np
 import pytest
@@ -110,6 +112,41 @@ def test_lts_conserves_on_the_device():
     sim.close()
 
 
+def test_lts_point_source_and_receivers():
+    from oracle.sources import PointSources, Receivers
+    w = make_workload("c4", n=4, N=2)
+    S = oracle_from(w)
+    xs = w.sources["xyz"][0]
+    recx = xs[None, :] + np.array([[310.0, -170.0, 90.0], [40.0, 35.0, -25.0]])
+    cl = _half(w)
+    cl[:] = 0
+    cent = w.mesh["xyz"][w.mesh["tets"]].mean(axis=1)
+    cl[np.linalg.norm(cent - xs, axis=1) < 4000.0] = 1     # the source region at twice the step
+    dt0 = w.dt / 2
+    t0 = 0.45
+    src = PointSources(S, **w.sources)
+    rec = Receivers(S, recx)
+    lts = LtsSolver(S, cl, dt0, sources=src)
+    U = S.project(w.ic)
+    want_seis = []
+    for k in range(3):
+        U = lts.macro_step(U, t0 + k * lts.macro_dt)
+        want_seis.append(rec.sample(U).numpy())
+    sim = _api().from_workload(w, "fp64", state=False)
+    sim.set_receivers(recx)
+    sim.set_state(_to_lib(S.project(w.ic)))
+    sim.set_time(t0)
+    sim.set_clusters(cl, dt0)
+    sim.step_lts(3)
+    e = errors(sim.get_state(), _to_lib(U), RefElement(w.N).V.numpy())
+    assert_within(e, 1e-10, "LTS with a point source")
+    got = sim.get_seismograms()
+    want = np.stack(want_seis)
+    assert np.abs(want).max() > 0
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10
+    sim.close()
+
+
 def test_lts_refusals():
     from paper_2502_09714_amd._lib import DGDError
     w = make_workload("c4", n=3, N=2)
@@ -119,9 +156,6 @@ def test_lts_refusals():
     with pytest.raises(DGDError, match="EINVAL"):
         sim.set_clusters(cl, w.dt)
     sim.set_clusters(np.zeros(w.ne, dtype=np.int32), w.dt)
-    with pytest.raises(DGDError, match="EINVAL"):           # the point source
-        sim.step_lts(1)
-    sim.set_point_sources(np.zeros((0, 3)), np.zeros((0, 6)), [], [], 0)
     sim.set_predictor("picard")
     with pytest.raises(DGDError, match="EINVAL"):
         sim.step_lts(1)
