@@ -386,12 +386,8 @@ template <int N, int P> struct FwdRegs {
 template <int N, int P> struct PredWaves {
   static constexpr int value = !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : 3));
 };
-#ifndef DGD_VOL_WAVES_N4_F32
-#define DGD_VOL_WAVES_N4_F32 2
-#endif
 template <int N, int P> struct VolWaves {
-  static constexpr int value =
-      P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 4 : DGD_VOL_WAVES_N4_F32));
+  static constexpr int value = P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 4 : 2));
 };
 
 // Prediction (Appendix A.1): Cauchy-Kovalevskaya derivatives of the element
@@ -769,12 +765,8 @@ template <int N, int P> struct Vol3LDS {
   T M[3][8];                                        // materials of the three elements
 };
 
-#ifndef DGD_VOL3_WAVES
-#define DGD_VOL3_WAVES 2
-#endif
-
 template <int N, int P, class LW = CdmLaw>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DGD_VOL3_WAVES)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void k_volume3(StepArgs<P> a) {
   using PR = Prec<P>;
   using T = typename PR::T;
