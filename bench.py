@@ -128,6 +128,23 @@ def load_traffic(kernel, workload, prec):
     return float(b.group(1))
 
 
+def load_error_table(workload, steps):
+    """A precision-error table of a longer run (too long for the default
+    bench) from its committed summary, if the kernel sources are unchanged
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"precision_errors_{workload}_{steps}steps.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    t = re.search(r"^table:\s*(\{.*\})\s*$", txt, flags=re.M)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    out = json.loads(t.group(1))
+    out["source"] = os.path.relpath(path, ROOT)
+    return out
+
+
 def run_precision(w, prec, steps, warmup, want_state=True):
     import torch
     from paper_2502_09714_amd.api import from_workload
@@ -177,11 +194,13 @@ def run_adjoint(w, prec, steps, every, observed=False):
     U0 = sim.get_state()
     base = dict(sim.material)
     obs = 0.0
+    print(f"adjoint {w.name}: set up", file=sys.stderr, flush=True)
     if observed:
         sim.set_material(**perturbed_material(base, seed=2))
         sim.step(steps)
         obs = sim.get_seismograms()
         sim.set_material(**base)
+        print(f"adjoint {w.name}: observed run done", file=sys.stderr, flush=True)
     sim.set_state(U0)
     sim.clear_seismograms()
     sim.forward_checkpointed(2, 1)          # warm-up of both sweeps
@@ -194,6 +213,7 @@ def run_adjoint(w, prec, steps, every, observed=False):
     sim.forward_checkpointed(steps, every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"adjoint {w.name}: checkpointed forward {t1 - t0:.1f} s", file=sys.stderr, flush=True)
     seis = sim.get_seismograms()
     sim.get_kernel_times()
     sim.set_profiling(True)
@@ -222,9 +242,12 @@ def fd_check(w, steps, grads, nelem, seed=31):
     from paper_2502_09714_amd.api import from_workload
     gmu, gcd, obs, U0, base = grads
     sim = from_workload(w, "fp64", state=False)
+    m = w.mesh
     if sim.nrec == 0:
-        m = w.mesh
-        sim.set_receivers(m["xyz"][m["tets"][[0, w.ne // 3, w.ne // 2, (2 * w.ne) // 3]]].mean(axis=1))
+        recx = m["xyz"][m["tets"][[0, w.ne // 3, w.ne // 2, (2 * w.ne) // 3]]].mean(axis=1)
+        sim.set_receivers(recx)
+    else:
+        recx = np.asarray(w.receivers)
     sim.set_check_interval(1 << 40)
 
     def misfit(mat):
@@ -235,7 +258,15 @@ def fd_check(w, steps, grads, nelem, seed=31):
         sim.step(steps)
         return 0.5 * float(((sim.get_seismograms() - obs) ** 2).sum())
 
-    idx = [int(e) for e in np.random.default_rng(seed).choice(w.ne, nelem, replace=False)]
+    # elements drawn at random among those the receivers can see within the
+    # run: centroid within half the distance a P wave travels in it
+    cent = m["xyz"][m["tets"]].mean(axis=1)
+    cp = np.sqrt((base["lambda0"] + 2 * base["mu0"]) / base["rho"]).max()
+    reach = 0.5 * cp * steps * w.dt
+    dist = np.min(np.linalg.norm(cent[:, None, :] - recx[None, :, :], axis=2), axis=1)
+    near = np.nonzero(dist < reach)[0]
+    idx = [int(e) for e in np.random.default_rng(seed).choice(near, min(nelem, len(near)),
+                                                              replace=False)]
     rows = []
     for which, g in (("mu0", gmu), ("Cd", gcd)):
         for e in idx:
@@ -248,6 +279,7 @@ def fd_check(w, steps, grads, nelem, seed=31):
             fd = (jp - jm) / (2 * h)
             rows.append({"param": which, "element": e, "adjoint": float(g[e]), "fd": fd,
                          "rel_diff": abs(float(g[e]) - fd) / max(abs(fd), 1e-300)})
+            print(f"fd check: {rows[-1]}", file=sys.stderr, flush=True)
     sim.close()
     return rows
 
@@ -386,8 +418,13 @@ def precision_errors(name, steps, precs, chunk=1 << 14):
         sim.set_check_interval(1 << 40)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.step(steps)
-        sim.synchronize()
+        done = 0
+        while done < steps:
+            k = min(100, steps - done)
+            sim.step(k)
+            sim.synchronize()
+            done += k
+            print(f"errors {name}: {p} {done}/{steps} steps", file=sys.stderr, flush=True)
         t[p] = time.perf_counter() - t0
         print(f"errors {name}: {p} {steps} steps in {t[p]:.1f} s", file=sys.stderr, flush=True)
     Q, L = ref.Q, ref.L
@@ -589,6 +626,8 @@ def main():
         eprecs = [q.strip() for q in args.error_precisions.split(",") if q.strip()]
         line["precision_errors"] = precision_errors(args.error_workload, args.error_steps, eprecs)
         print(f"precision errors: {line['precision_errors']}", file=sys.stderr, flush=True)
+        if args.error_steps < 1000:
+            line["precision_errors_1000_steps"] = load_error_table(args.error_workload, 1000)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n, args.cpu_steps)
     print(json.dumps(line), flush=True)
