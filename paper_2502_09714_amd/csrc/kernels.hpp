@@ -119,19 +119,22 @@ __device__ inline T wave_sum(T v) {
 __device__ constexpr int kVI[6] = {0, 1, 2, 0, 1, 2};
 __device__ constexpr int kVJ[6] = {0, 1, 2, 1, 2, 0};
 
-// The time-point buffer W and A*_e: separate, or (AW) sharing storage, which
-// the forward kernel can afford because it copies A*_e to registers before
-// the first time-point state is formed (and the adjoint's register form,
-// which puts its time-point states elsewhere).
-template <class T, int NW, bool AW> struct PredWA {
+// The time-point buffer W and A*_e: separate (AW = 0), or sharing storage
+// (AW = 1: the adjoint's register form, which puts its time-point states
+// elsewhere), or no W at all (AW = 2: the forward prediction, which writes its
+// time-point states from registers).
+template <class T, int NW, int AW> struct PredWA {
   T W[NW];                // time-point state / scratch
   T A[300];               // A*_e (3 x 10 x 10)
 };
-template <class T, int NW> struct PredWA<T, NW, true> {
+template <class T, int NW> struct PredWA<T, NW, 1> {
   union {
     T W[NW];
     T A[300];
   };
+};
+template <class T, int NW> struct PredWA<T, NW, 2> {
+  T A[300];
 };
 
 // LDS working set of the predictor of one element (one wavefront).  Matrices
@@ -141,7 +144,7 @@ template <class T, int NW> struct PredWA<T, NW, true> {
 // ND = 1 keeps only the one being formed (it overwrites its predecessor once
 // the right-hand sides are built) and leaves a copy of each in registers, DPL
 // values per lane, for the Taylor sums.
-template <int N, int P, int ND = N + 1, bool AW = false>
+template <int N, int P, int ND = N + 1, int AW = 0>
 struct PredLDS : PredWA<typename Prec<P>::T, round_up(Dims<N>::L, Prec<P>::KS) * 16, AW> {
   using T = typename Prec<P>::T;
   static constexpr int L = Dims<N>::L, NCH = Dims<N>::NCH;
@@ -150,7 +153,12 @@ struct PredLDS : PredWA<typename Prec<P>::T, round_up(Dims<N>::L, Prec<P>::KS) *
   static constexpr int DS = 16;          // D, W: read linearly and as matrix-core B operands
   static constexpr int DPL = KPL * DS / 64;
   static_assert(KPL * DS % 64 == 0, "derivatives split evenly over the lanes");
-  static constexpr int BIG = 64 * R > 3 * KPL * R ? 64 * R : 3 * KPL * R;
+  // row stride of the CK right-hand sides Y_e: the forward prediction keeps
+  // their 10 quantity columns and one zero column (odd stride; the matrix
+  // cores read the zero column for the other 6), the adjoint reuses the
+  // buffer with stride R
+  static constexpr int RB = AW == 2 ? 11 : R;
+  static constexpr int BIG = 64 * R > 3 * KPL * RB ? 64 * R : 3 * KPL * RB;
   T D[ND][KPL * DS];      // time derivatives D^i in buffer i % ND, [l][16] layout
   T B[BIG];               // nodal values, tangent blocks, CK right-hand sides (aliased)
   T R_[NCH * 64];         // nodal damage rate at t_n
@@ -160,7 +168,7 @@ struct PredLDS : PredWA<typename Prec<P>::T, round_up(Dims<N>::L, Prec<P>::KS) *
 
 // A*_e = sum_d Theta^-1_ed Bbar^d, rows p, columns q (10 x 10 each), from
 // Theta^-1 (S.J) and the cell-averaged tangent (S.Acc)
-template <int N, int P, int ND, bool AW>
+template <int N, int P, int ND, int AW>
 __device__ inline void build_Astar(PredLDS<N, P, ND, AW>& S, const MatP<typename Prec<P>::T>& m,
                                    int lane) {
   using T = typename Prec<P>::T;
@@ -186,7 +194,7 @@ __device__ inline void build_Astar(PredLDS<N, P, ND, AW>& S, const MatP<typename
 // (REGS false, ND = N + 1; dreg unused and may be null), or in
 // dreg[i * DPL + j] = D^i[lane + 64 j] (REGS true, ND = 1).  With AW, S.A is
 // not kept past the recursion.
-template <int N, int P, int ND, bool REGS, bool AW = false, class LW = CdmLaw>
+template <int N, int P, int ND, bool REGS, int AW = 0, class LW = CdmLaw>
 __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLDS<N, P, ND, AW>& S,
                                        const MatP<typename Prec<P>::T>& m, int lane,
                                        typename Prec<P>::T* dreg) {
@@ -200,7 +208,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   constexpr int KSQA = 64 / PA::KS;
   using SL = PredLDS<N, P, ND, AW>;
-  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
+  constexpr int R = SL::R, RB = SL::RB, DS = SL::DS, DPL = SL::DPL;
   static_assert(REGS ? ND == 1 : ND == N + 1, "one buffer with register copies, or all");
   T* const sX = S.B;
   const Law<T> law{a.amax, a.smin};
@@ -284,7 +292,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
   // The right-hand-side buffer held nodal values before: clear it so that its
   // padding rows and columns (read by the matrix cores against zero entries
   // of K) are zero, not stale values.
-  for (int i = lane; i < 3 * KPL * R; i += 64) S.B[i] = T(0);
+  for (int i = lane; i < 3 * KPL * RB; i += 64) S.B[i] = T(0);
   __syncthreads();
 
   // Cauchy-Kovalevskaya recursion.  Y_e = D^{i-1} A*_e^T on the vector ALUs:
@@ -305,13 +313,13 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
         T s = T(0);
 #pragma unroll
         for (int q = 0; q < 10; ++q) s += Dr[q] * Arow[q];
-        S.B[(pe * KPL + l) * R + pp] = s;
+        S.B[(pe * KPL + l) * RB + pp] = s;
       }
     }
     __syncthreads();
     Acc C[MT];
     zero_C<P, MT>(C);
-    wave_gemm<P, MT, 3 * KSL>(a.Kpk, S.B, C, lane);
+    wave_gemm<P, MT, 3 * KSL, RB, 3 * KSL, RB == R ? 16 : 10>(a.Kpk, S.B, C, lane);
     // damage source at t_n, projected on the modes in the same accumulators
     // (column 9; the accurate precision's inputs, FP32 accumulation in the
     // BF16 form): D^1 = -(sum_e K^e Y_e) + P r
@@ -332,7 +340,7 @@ __device__ inline void predictor_stage(const StepArgs<P>& a, long long e, PredLD
 // The predictor's results kept by an earlier launch of k_predict on the
 // same state (D^1..D^N and the cell-averaged tangent): load them instead of
 // recomputing them.  Leaves S (and dreg) as predictor_stage does, except S.R_.
-template <int N, int P, int ND, bool REGS, bool AW>
+template <int N, int P, int ND, bool REGS, int AW>
 __device__ inline void predictor_restore(const StepArgs<P>& a, long long e,
                                          PredLDS<N, P, ND, AW>& S,
                                          const MatP<typename Prec<P>::T>& m,
@@ -383,8 +391,12 @@ template <int N, int P> struct FwdRegs {
 // Launch shapes of the two halves of the element update.  The prediction
 // keeps the derivatives in registers (45 values per lane at degree 4 in FP32)
 // with one LDS buffer; the volume half holds only per-point time integrals.
+// Degree 4 (c5 step, ms): FP32 prediction 93.3 at 4 wavefronts per SIMD
+// against 95.2 at 3; the split-BF16 one 82.2 at 3 against 90.6 at 4 (its
+// register budget at 4 spills).
 template <int N, int P> struct PredWaves {
-  static constexpr int value = !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : 3));
+  static constexpr int value =
+      !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : (P == PREC_BF16 ? 3 : 4)));
 };
 template <int N, int P> struct VolWaves {
   static constexpr int value = P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 4 : 2));
@@ -405,7 +417,7 @@ void k_predict(StepArgs<P> a) {
   constexpr int KS = PR::KS, KPL = round_up(L, KS);
   constexpr bool REGS = FwdRegs<N, P>::value;
   constexpr int ND = FwdRegs<N, P>::ND;
-  using SL = PredLDS<N, P, ND, true>;
+  using SL = PredLDS<N, P, ND, 2>;
   constexpr int DPL = SL::DPL;
   static_assert(SL::DS == 16, "time-point states are copied to HBM row by row");
   __shared__ SL S;
@@ -415,7 +427,7 @@ void k_predict(StepArgs<P> a) {
   const long long e = elem_index(a);
   if (e < 0) return;
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  predictor_stage<N, P, ND, REGS, true, LW>(a, e, S, m, lane, dreg);
+  predictor_stage<N, P, ND, REGS, 2, LW>(a, e, S, m, lane, dreg);
   // D^i[idx] for idx = lane + 64 j
   auto Dv = [&](int i, int j) -> T {
     if constexpr (REGS)
@@ -754,15 +766,20 @@ void k_volume(StepArgs<P> a) {
 // 10 j + p for element j, quantity p; 30 of 32 columns used): each A fragment
 // feeds two matrix-core products for three elements instead of one product
 // (10 of 16 columns) for one.
+// Column 32 of X (the padding column, never written by the matrix stages)
+// holds Theta^-1 of the three elements in rows 0..26 and their materials in
+// rows 27..50, so that the LDS of one wavefront stays within a twelfth of a
+// compute unit's (three wavefronts per SIMD at degree 4).
 template <int N, int P> struct Vol3LDS {
   using T = typename Prec<P>::T;
   static constexpr int RS = 33;                     // 32 columns, odd stride
   static constexpr int KPL = round_up(Dims<N>::L, Prec<P>::KS);
   static constexpr int XR = 64 > KPL ? 64 : KPL;
+  static_assert(XR >= 51, "Theta^-1 and materials fit the padding column of X");
   T X[XR * RS];                                     // point values / integrands of a chunk
   T W[KPL * RS];                                    // time-point states of the three elements
-  T J[3][9];
-  T M[3][8];                                        // materials of the three elements
+  __device__ T& J(int j, int k) { return X[(9 * j + k) * RS + 32]; }
+  __device__ T& M(int j, int k) { return X[(27 + 8 * j + k) * RS + 32]; }
 };
 
 template <int N, int P, class LW = CdmLaw>
@@ -799,21 +816,21 @@ void k_volume3(StepArgs<P> a) {
   const Law<T> law{a.amax, a.smin};
   if (lane < 24) {
     const long long ej = el[lane / 8] >= 0 ? el[lane / 8] : el[0];
-    S.M[lane / 8][lane % 8] = (T)a.mat[ej * 8 + lane % 8];
+    S.M(lane / 8, lane % 8) = (T)a.mat[ej * 8 + lane % 8];
   }
   auto mat_of = [&](int j) {
     MatP<T> mm;
-    mm.rho = S.M[j][0];
-    mm.lam = S.M[j][1];
-    mm.mu = S.M[j][2];
-    mm.gr = S.M[j][3];
-    mm.xi0 = S.M[j][4];
-    mm.cd = S.M[j][5];
+    mm.rho = S.M(j, 0);
+    mm.lam = S.M(j, 1);
+    mm.mu = S.M(j, 2);
+    mm.gr = S.M(j, 3);
+    mm.xi0 = S.M(j, 4);
+    mm.cd = S.M(j, 5);
     return mm;
   };
   if (lane < 27) {
     const long long ej = el[lane / 9];
-    S.J[lane / 9][lane % 9] = ej >= 0 ? (T)a.geo[ej * 16 + lane % 9] : T(0);
+    S.J(lane / 9, lane % 9) = ej >= 0 ? (T)a.geo[ej * 16 + lane % 9] : T(0);
   }
   for (int i = lane; i < KPL * RS; i += 64) sW[i] = T(0);
 
@@ -868,7 +885,26 @@ void k_volume3(StepArgs<P> a) {
     }
   }
 
-  // volume contraction sum_e Sw^e G^e and the damage-source projection
+  // damage source first (its accumulators are free again before those of
+  // the volume contraction are taken): the three elements' rate integrals in
+  // columns 0..2 of one 16-column tile, projected, times dt, to columns 0..2
+  // of W (the damage columns 10 j + 9 of the volume contraction are zero: no
+  // damage flux)
+  {
+    typename PA::Acc Sc[MT];
+    zero_C<PA_, MT>(Sc);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sX[lane * RS + k] = k < 3 ? sacc[c][k] : T(0);
+      __syncthreads();
+      wave_gemm<PA_, MT, KSQA, RS>(a.Ppk + (size_t)c * MT * KSQA * 64, sX, Sc, lane);
+    }
+    store_C<PA_, MT, RS, 3>(Sc, sW, L, (T)a.dt, lane);
+  }
+
+  // volume contraction sum_e Sw^e G^e
   Acc Vc[MT][2];
   zero_C2<P, MT>(Vc);
 #pragma unroll 1
@@ -877,10 +913,10 @@ void k_volume3(StepArgs<P> a) {
     for (int c = 0; c < NCH; ++c) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const T ir = T(1) / S.M[j][0];
+        const T ir = T(1) / S.M(j, 0);
         T Jr[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Jr[d] = S.J[j][ee * 3 + d];
+        for (int d = 0; d < 3; ++d) Jr[d] = S.J(j, ee * 3 + d);
         T* row = sX + lane * RS + 10 * j;
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
@@ -903,17 +939,6 @@ void k_volume3(StepArgs<P> a) {
       __syncthreads();
     }
   }
-  // damage source: the rate integrals in the damage columns 10 j + 9
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-    for (int k = 0; k < 32; ++k) sX[lane * RS + k] = T(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) sX[lane * RS + 10 * j + 9] = sacc[c][j];
-    __syncthreads();
-    wave_gemm2<PA_, MT, KSQA, RS>(a.Ppk + (size_t)c * MT * KSQA * 64, sX, Vc, lane);
-    __syncthreads();
-  }
   store_C2<P, MT, RS>(Vc, sX, L, (T)a.dt, lane);
   __syncthreads();
   // U^n + volume for the nine wave quantities; the damage increment joins the
@@ -928,7 +953,7 @@ void k_volume3(StepArgs<P> a) {
       const int p = idx / L, l = idx - p * L;
       W9[idx] = U9[idx] + sX[l * RS + 10 * j + p];
     }
-    if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sX[lane * RS + 10 * j + 9];
+    if (lane < L) a.Wa[e * L + lane] = a.Ua[e * L + lane] + (double)sW[lane * RS + j];
   }
 }
 

@@ -68,6 +68,15 @@ __host__ __device__ inline uint16_t f32_to_bf16(float x) {
 
 template <int P> struct Prec;
 
+// Column of a B fragment a lane reads from a [K][RS] matrix that holds NC < 16
+// columns: the lanes of the missing columns read column NC, a padding column
+// that holds zero in every row.
+template <int NC>
+__device__ inline int bcol(int lane) {
+  const int n = lane & 15;
+  return NC < 16 && n > NC ? NC : n;
+}
+
 template <> struct Prec<PREC_F64> {
   using T = double;
   using Acc = f64x4;
@@ -78,9 +87,9 @@ template <> struct Prec<PREC_F64> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   // B fragment from a [K][RS] row-major matrix (LDS or global)
-  template <int RS>
+  template <int RS, int NC = 16>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
-    return B[(KS * s + (lane >> 4)) * RS + (lane & 15)];
+    return B[(KS * s + (lane >> 4)) * RS + bcol<NC>(lane)];
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
     return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0;
@@ -96,9 +105,9 @@ template <> struct Prec<PREC_F32> {
   __device__ static inline Acc mma(AF a, AF b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  template <int RS>
+  template <int RS, int NC = 16>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
-    return B[(KS * s + (lane >> 4)) * RS + (lane & 15)];
+    return B[(KS * s + (lane >> 4)) * RS + bcol<NC>(lane)];
   }
   __device__ static inline AF loadB9(const T* v, int s, int lane) {
     return (lane & 15) == 9 ? v[KS * s + (lane >> 4)] : 0.0f;
@@ -116,9 +125,9 @@ template <> struct Prec<PREC_BF16> {
     c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
   }
-  template <int RS>
+  template <int RS, int NC = 16>
   __device__ static inline AF loadB(const T* B, int s, int lane) {
-    int k0 = KS * s + 4 * (lane >> 4), n = lane & 15;
+    int k0 = KS * s + 4 * (lane >> 4), n = bcol<NC>(lane);
     return split4(B[(k0 + 0) * RS + n], B[(k0 + 1) * RS + n], B[(k0 + 2) * RS + n],
                   B[(k0 + 3) * RS + n]);
   }
@@ -144,17 +153,19 @@ template <class T> struct Lds { static constexpr int RS = 18; };
 template <int P> struct Accurate { static constexpr int value = P == PREC_BF16 ? PREC_F32 : P; };
 
 // C (tiles of 16 rows) += A_packed x B, A packed as [tile][kstep][lane], B a
-// [K][RS] row-major matrix (RS = 16 for the global time-point states).
+// [K][RS] row-major matrix (RS = 16 for the global time-point states) whose
+// columns from NC on are zero (column NC is stored and zero, see bcol).
 // KSTEPS is a compile-time constant so that the loop unrolls and the A-fragment
 // loads are issued ahead of the matrix-core instructions that consume them.
-template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS, int KSTRIDE = KSTEPS>
+template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS, int KSTRIDE = KSTEPS,
+          int NC = 16>
 __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
                                  const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT],
                                  int lane) {
   using PR = Prec<P>;
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    typename PR::AF b = PR::template loadB<RS>(B, s, lane);
+    typename PR::AF b = PR::template loadB<RS, NC>(B, s, lane);
 #pragma unroll
     for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
   }
