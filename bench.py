@@ -267,6 +267,7 @@ def fd_check(w, steps, grads, nelem, seed=31):
     near = np.nonzero(dist < reach)[0]
     idx = [int(e) for e in np.random.default_rng(seed).choice(near, min(nelem, len(near)),
                                                               replace=False)]
+    j0 = misfit(base)
     rows = []
     for which, g in (("mu0", gmu), ("Cd", gcd)):
         for e in idx:
@@ -277,8 +278,12 @@ def fd_check(w, steps, grads, nelem, seed=31):
             mp[which][e] -= 2 * h
             jm = misfit(mp)
             fd = (jp - jm) / (2 * h)
+            # a difference of the misfit below ~1e-12 of the misfit itself is
+            # rounding of the FP64 runs, not a derivative
             rows.append({"param": which, "element": e, "adjoint": float(g[e]), "fd": fd,
-                         "rel_diff": abs(float(g[e]) - fd) / max(abs(fd), 1e-300)})
+                         "rel_diff": abs(float(g[e]) - fd) / max(abs(fd), 1e-300),
+                         "misfit": j0, "adjoint_delta_misfit": abs(float(g[e])) * 2 * h,
+                         "resolved": abs(float(g[e])) * 2 * h > 1e-12 * abs(j0)})
             print(f"fd check: {rows[-1]}", file=sys.stderr, flush=True)
     sim.close()
     return rows

@@ -217,16 +217,184 @@ __global__ __launch_bounds__(64) void k_adj_lift(AdjArgs<P> A) {
     store_C<P, MT, 16>(Cz[z], A.lzf + ((size_t)e * Nt + z) * KPL * 16, KPL, T(1), lane);
 }
 
+// At degree 4 the adjoint of the volume terms runs as two launches, each with
+// its own register and LDS budget (one launch holds more than a SIMD's
+// registers): k_adj_points (the volume and source cotangents at the time
+// points, dJ/dU_z to HBM), then k_adj_volume<N, P, false> (the predictor
+// reversed).  Below degree 4 k_adj_volume<N, P, true> does both.
+template <int N> struct AdjSplit {
+  static constexpr bool value = N >= 4;
+};
+
+// LDS of k_adj_points: lambda^{n+1}, then the time-point state being
+// evaluated (then its cotangent); the point values / integrands of a chunk;
+// the per-point cotangents that lambda^{n+1} gives.
+template <int N, int P> struct AdjPtLDS {
+  using T = typename Prec<P>::T;
+  static constexpr int KPL = round_up(Dims<N>::L, Prec<P>::KS);
+  static constexpr int R = Lds<T>::RS;
+  union {
+    T Lam[KPL * 16];
+    T Z[KPL * 16];              // lambda^{n+1} is spent before the first time point
+  };
+  T X[64 * R];
+  T Lp[Dims<N>::NCH][10][64];   // per point: velocity, stress and rate cotangents
+};
+
+// One wavefront per element: the volume and source terms transposed.
+// dJ/dG^e at the volume points is dt Sw^e^T lambda, folded at once into the
+// cotangents of the velocity and of the stress per point and unit time weight
+// (the flux is linear in both), and dJ/dr is dt Pw^T lambda_alpha; at every
+// (z, q) the pointwise VJP of sigma and r_alpha at the time-point state U_z
+// (read from HBM, where k_predict left it) and the transposed nodal
+// evaluation give the volume part of dJ/dU_z, which joins the face part in
+// lzf[e][z]; the material cotangents of the volume points join gmu, gcd.
+template <int N, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P == PREC_F64 ? 2 : 4)))
+void k_adj_points(AdjArgs<P> A) {
+  using PR = Prec<P>;
+  using T = typename PR::T;
+  using Acc = typename PR::Acc;
+  using DM = Dims<N>;
+  const StepArgs<P>& a = A.s;
+  constexpr int L = DM::L, Q = DM::Q, Nt = DM::Nt, NCH = DM::NCH, MT = DM::MT;
+  constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
+  constexpr int DS = 16, DPL = KPL * DS / 64;
+  using SL = AdjPtLDS<N, P>;
+  constexpr int R = SL::R;
+  __shared__ SL S;
+  T* const sX = S.X;
+  T* const sZ = S.Z;
+  const int lane = threadIdx.x;
+  const long long e = elem_of_block(a.E);
+  if (e >= a.E) return;
+  const Law<T> law{a.amax, a.smin};
+  const MatP<T> m = load_mat<T>(a.mat + e * 8);
+  T Ji[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ji[k] = (T)a.geo[e * 16 + k];
+  const T ir = T(1) / m.rho;
+  for (int i = lane; i < KPL * DS; i += 64) S.Lam[i] = A.lam[(size_t)e * KPL * 16 + i];
+  T gmu = T(0), gcd = T(0);
+  __syncthreads();
+
+  // per point and unit time weight: Lp[c][k][lane], k = 0..2 velocity,
+  // 3..8 stress, 9 damage rate
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    T LV[3], LS[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) LV[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) LS[k] = T(0);
+#pragma unroll 1
+    for (int ee = 0; ee < 3; ++ee) {
+      Acc C[4];
+      zero_C<P, 4>(C);
+      wave_gemm<P, 4, KSL, DS>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, S.Lam, C, lane);
+      store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
+      __syncthreads();
+      // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
+      T Jr[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Jr[d] = ee == 0 ? Ji[d] : (ee == 1 ? Ji[3 + d] : Ji[6 + d]);
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const int ii = kVI[p], jj = kVJ[p];
+        const T lg = sX[lane * R + p];
+        LV[ii] += T(-0.5) * Jr[jj] * lg;
+        LV[jj] += T(-0.5) * Jr[ii] * lg;
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        const T lg = sX[lane * R + 6 + ii] * (-ir);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) LS[sym_idx(ii, d)] += lg * Jr[d];
+      }
+      __syncthreads();
+    }
+    Acc C[4];
+    zero_C<P, 4>(C);
+    wave_gemm<P, 4, KSL, DS>(A.PTpk + (size_t)c * 4 * KSL * 64, S.Lam, C, lane);
+    store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S.Lp[c][k][lane] = LV[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S.Lp[c][3 + k][lane] = LS[k];
+    S.Lp[c][9][lane] = sX[lane * R + 9];
+    __syncthreads();
+  }
+
+  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+#pragma unroll 1
+  for (int z = 0; z < Nt; ++z) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) sZ[lane + 64 * j] = Uze[z * KPL * 16 + lane + 64 * j];
+    __syncthreads();
+    const T g = a.gamma[z];
+    Acc Cl[MT];
+    zero_C<P, MT>(Cl);
+#pragma unroll 1
+    for (int c = 0; c < NCH; ++c) {
+      Acc C[4];
+      zero_C<P, 4>(C);
+      wave_gemm_tiles<P, 4, KSL, DS>(a.Vpk + (size_t)c * 4 * KSL * 64, sZ, C, lane);
+      store_C<P, 4>(C, sX, 64, T(1), lane);
+      __syncthreads();
+      const int q = 64 * c + lane;
+      T gu[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) gu[k] = T(0);
+      if (q < Q) {
+        T u[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) u[k] = sX[lane * R + k];
+        T ls[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ls[k] = g * S.Lp[c][3 + k][lane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gu[6 + k] += g * S.Lp[c][k][lane];
+        const Parts<T> pp = cdm_parts(u, law);
+        stress_vjp_p(pp, u, m, ls, gu, gmu);
+        rate_vjp_p(pp, u, m, g * S.Lp[c][9][lane], gu, gcd);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sX[lane * R + k] = k < 10 ? gu[k] : T(0);
+      __syncthreads();
+      wave_gemm_tiles<P, MT, KSQ>(A.VTpk + (size_t)c * MT * KSQ * 64, sX, Cl, lane);
+      __syncthreads();
+    }
+    // the time-point state is spent: the volume part of dJ/dU_z goes there,
+    // then joins the face part
+    store_C<P, MT, DS>(Cl, sZ, KPL, T(1), lane);
+    __syncthreads();
+    T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) lz[lane + 64 * j] += sZ[lane + 64 * j];
+    __syncthreads();
+  }
+  const T gm = wave_sum(gmu), gc = wave_sum(gcd);
+  if (lane == 0) {
+    A.gmu[e] += (double)gm;
+    A.gcd[e] += (double)gc;
+  }
+}
+
 // Derivatives D^i of the predictor in registers (one LDS buffer, which also
 // takes the time-point states), or all of them in LDS: as in the forward
-// kernel, except FP64, whose adjoint registers would not fit.
+// kernel, except FP64, whose adjoint registers would not fit, and the fused
+// degree-4 form.
 template <int N, int P> struct AdjRegs {
-  static constexpr bool value = P != PREC_F64 && N <= 3;
+  static constexpr bool value = P != PREC_F64 && (N <= 3 || AdjSplit<N>::value);
   static constexpr int ND = value ? 1 : N + 1;
 };
 
-template <int N, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AdjRegs<N, P>::value ? 3 : 1)))
+// PTS: this launch also transposes the volume and source terms at the time
+// points (else k_adj_points has, and lzf holds all of dJ/dU_z).
+template <int N, int P, bool PTS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AdjRegs<N, P>::value ? (PTS ? 3 : 2) : 1)))
 void k_adj_volume(AdjArgs<P> A) {
   using PR = Prec<P>;
   using T = typename PR::T;
@@ -289,6 +457,24 @@ void k_adj_volume(AdjArgs<P> A) {
   T gmu = T(0), gcd = T(0);
   __syncthreads();
 
+  if constexpr (!PTS) {
+    // dJ/dU_z complete in lzf: the Taylor series reversed,
+    // dJ/dD^i += (tau_z dt)^i / i! dJ/dU_z
+    for (int z = 0; z < Nt; ++z) {
+      T cz[N + 1];
+      cz[0] = T(1);
+      const T h = a.tau[z] * (T)a.dt;
+#pragma unroll
+      for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
+      const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
+      for (int idx = lane; idx < KPL * DS; idx += 64) {
+        const T v = lz[idx];
+#pragma unroll
+        for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
+      }
+    }
+    __syncthreads();
+  } else {
   // dJ/dG^e at the volume points: dt Sw^e^T lambda, folded at once into the
   // cotangents of the velocity (LV) and of the stress (LS) at each point, per
   // unit time weight (the flux is linear in both);  dJ/dr: dt Pw^T lambda_alpha
@@ -393,6 +579,7 @@ void k_adj_volume(AdjArgs<P> A) {
       for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
     }
     __syncthreads();
+  }
   }
 
   // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source).

@@ -721,7 +721,14 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
                          (const int*)h->faces.p, h->nfaces);
       hipLaunchKernelGGL((k_adj_lift<N, P>), grid, block, 0, h->stream, A);
     });
-    timed(h, 6, [&] { hipLaunchKernelGGL((k_adj_volume<N, P>), grid, block, 0, h->stream, A); });
+    timed(h, 6, [&] {
+      if constexpr (AdjSplit<N>::value) {
+        hipLaunchKernelGGL((k_adj_points<N, P>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_adj_volume<N, P, false>), grid, block, 0, h->stream, A);
+      } else {
+        hipLaunchKernelGGL((k_adj_volume<N, P, true>), grid, block, 0, h->stream, A);
+      }
+    });
     HIPCHK(h, hipGetLastError());
     return DGD_OK;
   }

@@ -134,8 +134,9 @@ def _smooth_state(S, w, seed):
         return S.step(U + bg)
 
 
-def test_adjoint_step_fp32():
-    w = make_workload("c2", n=3, N=2)
+@pytest.mark.parametrize("N", [2, 4])
+def test_adjoint_step_fp32(N):
+    w = make_workload("c2", n=3, N=N)
     S = diff_from_workload(w)
     U = _smooth_state(S, w, 21)
     lam = torch.randn(U.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(3))
