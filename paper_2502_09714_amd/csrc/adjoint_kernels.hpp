@@ -405,22 +405,37 @@ void k_adj_volume(AdjArgs<P> A) {
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS, KSQ = 64 / KS;
   constexpr bool REGS = AdjRegs<N, P>::value;
   constexpr int ND = AdjRegs<N, P>::ND;
-  // with the derivatives in registers the time-point buffer W is unused and
-  // A*_e may share its storage
-  using SL = PredLDS<N, P, ND, REGS>;
-  constexpr int R = SL::R, DS = SL::DS, DPL = SL::DPL;
+  // with the derivatives in registers the time-point buffer W is unused, and
+  // the right-hand sides Y_e and their cotangents keep 10 columns and one
+  // zero column (row stride RB = 11), as do the cotangents dJ/dD^i (row
+  // stride RL); else both keep 16 columns
+  constexpr int AWM = REGS ? 2 : 0;
+  using SL = PredLDS<N, P, ND, AWM>;
+  constexpr int R = SL::R, RB = SL::RB, DS = SL::DS, DPL = SL::DPL;
+  constexpr int NCB = RB == R ? 16 : 10;
+  constexpr int RL = REGS ? 11 : DS, NCL = REGS ? 10 : 16;
   static_assert(DS == 16, "adjoint states are exchanged with HBM row by row");
   __shared__ SL S;
   // sLD[i] = dJ/dD^i; sLD[0] starts as lambda^{n+1} (the identity path) and
   // ends as lambda^n minus the nodal path of the tangent and source at t_n
-  __shared__ T sLD[N + 1][KPL * DS];
+  __shared__ T sLD[N + 1][KPL * RL];
+  // position in sLD of entry idx of a [KPL][16] matrix (-1: a column not kept)
+  auto lpos = [&](int idx) -> int {
+    const int l = idx >> 4, p = idx & 15;
+    return (RL == 16 || p < 10) ? l * RL + p : -1;
+  };
   T dreg[REGS ? (N + 1) * DPL : 1];
   T* const sX = S.B;
   T* const sLam = sLD[0];
   T* const sLA = S.B;     // dJ/dA*_e, between the CK reversal and the t_n pass
   T* const sLds = S.Acc;  // its cell-average cotangent (the average itself is spent)
   // time-point state, then dJ/dU_z; at the end the nodal path at t_n
-  T* const sZ = REGS ? S.D[0] : S.W;
+  T* const sZ = [&]() -> T* {
+    if constexpr (REGS)
+      return S.D[0];
+    else
+      return S.W;
+  }();
   const int lane = threadIdx.x;
   // D^i[idx] for idx = lane + 64 j
   auto Dv = [&](int i, int j) -> T {
@@ -447,9 +462,13 @@ void k_adj_volume(AdjArgs<P> A) {
   if (A.Dkept)
     predictor_restore<N, P, ND, REGS>(a, e, S, m, A.Dkept, A.Akept, lane, dreg);
   else
-    predictor_stage<N, P, ND, REGS, REGS>(a, e, S, m, lane, dreg);
-  for (int i = lane; i < KPL * DS; i += 64) sLam[i] = A.lam[(size_t)e * KPL * 16 + i];
-  for (int i = lane; i < N * KPL * DS; i += 64) (&sLD[1][0])[i] = T(0);
+    predictor_stage<N, P, ND, REGS, AWM>(a, e, S, m, lane, dreg);
+  for (int i = lane; i < (N + 1) * KPL * RL; i += 64) (&sLD[0][0])[i] = T(0);
+  __syncthreads();
+  for (int idx = lane; idx < KPL * DS; idx += 64) {
+    const int o = lpos(idx);
+    if (o >= 0) sLam[o] = A.lam[(size_t)e * KPL * 16 + idx];
+  }
   T Ji[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Ji[k] = S.J[k];
@@ -468,9 +487,11 @@ void k_adj_volume(AdjArgs<P> A) {
       for (int i = 1; i <= N; ++i) cz[i] = cz[i - 1] * h / T(i);
       const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
       for (int idx = lane; idx < KPL * DS; idx += 64) {
+        const int o = lpos(idx);
+        if (o < 0) continue;
         const T v = lz[idx];
 #pragma unroll
-        for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
+        for (int i = 0; i <= N; ++i) sLD[i][o] += cz[i] * v;
       }
     }
     __syncthreads();
@@ -490,7 +511,8 @@ void k_adj_volume(AdjArgs<P> A) {
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[4];
       zero_C<P, 4>(C);
-      wave_gemm<P, 4, KSL, DS>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C, lane);
+      wave_gemm<P, 4, KSL, RL, KSL, NCL>(A.STpk + (size_t)(ee * NCH + c) * 4 * KSL * 64, sLam, C,
+                                         lane);
       store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
       __syncthreads();
       // G^e_(ij) = -(J_ej v_i + J_ei v_j)/2,  G^e_(v_i) = -(1/rho) sum_d J_ed sigma_id
@@ -512,7 +534,7 @@ void k_adj_volume(AdjArgs<P> A) {
     }
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL, DS>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
+    wave_gemm<P, 4, KSL, RL, KSL, NCL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLam, C, lane);
     store_C<P, 4>(C, sX, 64, (T)a.dt, lane);
     __syncthreads();
     Ls[c] = sX[lane * R + 9];
@@ -574,9 +596,11 @@ void k_adj_volume(AdjArgs<P> A) {
     __syncthreads();
     const T* lz = A.lzf + ((size_t)e * Nt + z) * KPL * 16;
     for (int idx = lane; idx < KPL * DS; idx += 64) {
+      const int o = lpos(idx);
+      if (o < 0) continue;
       const T v = sZ[idx] + lz[idx];
 #pragma unroll
-      for (int i = 0; i <= N; ++i) sLD[i][idx] += cz[i] * v;
+      for (int i = 0; i <= N; ++i) sLD[i][o] += cz[i] * v;
     }
     __syncthreads();
   }
@@ -584,7 +608,7 @@ void k_adj_volume(AdjArgs<P> A) {
 
   // Cauchy-Kovalevskaya recursion reversed: D^i = -sum_e K^e D^{i-1} A*_e^T (+ source).
   // All three contractions on the matrix cores; dJ/dA*_e stays in registers.
-  for (int i = lane; i < 3 * KPL * R; i += 64) S.B[i] = T(0);   // padding rows of dJ/dY_e
+  for (int i = lane; i < 3 * KPL * RB; i += 64) S.B[i] = T(0);   // padding rows of dJ/dY_e
   Acc CA[3];
   zero_C<P, 3>(CA);
   __syncthreads();
@@ -595,8 +619,8 @@ void k_adj_volume(AdjArgs<P> A) {
     for (int ee = 0; ee < 3; ++ee) {
       Acc C[MT];
       zero_C<P, MT>(C);
-      wave_gemm<P, MT, KSL, DS>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
-      store_C<P, MT>(C, S.B + ee * KPL * R, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
+      wave_gemm<P, MT, KSL, RL, KSL, NCL>(A.KTpk + (size_t)ee * MT * KSL * 64, sLD[i], C, lane);
+      store_C<P, MT, RB, NCB>(C, S.B + ee * KPL * RB, L, T(-1), lane);   // dJ/dY_e = -K^e^T dJ/dD^i
     }
     __syncthreads();
     // dJ/dA*_e[p][q] += sum_l dJ/dY_e[l][p] D^{i-1}[l][q]   (A = dJ/dY_e^T from LDS)
@@ -604,7 +628,7 @@ void k_adj_volume(AdjArgs<P> A) {
     for (int ee = 0; ee < 3; ++ee)
 #pragma unroll
       for (int st = 0; st < KSL; ++st) {
-        const T av = S.B[(ee * KPL + KS * st + (lane >> 4)) * R + (lane & 15)];
+        const T av = S.B[(ee * KPL + KS * st + (lane >> 4)) * RB + bcol<NCB>(lane)];
         CA[ee] = PR::mma(av, PR::template loadB<DS>(Dm, st, lane), CA[ee]);
       }
     // dJ/dD^{i-1}[l][q] += sum_e sum_p dJ/dY_e[l][p] A*_e[p][q]   (K = p, 3 steps)
@@ -621,7 +645,7 @@ void k_adj_volume(AdjArgs<P> A) {
 #pragma unroll
           for (int t = 0; t < MT; ++t) {
             const int row = 16 * t + col;
-            const T av = (row < L && k < 10) ? S.B[(ee * KPL + row) * R + k] : T(0);
+            const T av = (row < L && k < 10) ? S.B[(ee * KPL + row) * RB + k] : T(0);
             CD[t] = PR::mma(av, bv, CD[t]);
           }
         }
@@ -630,7 +654,7 @@ void k_adj_volume(AdjArgs<P> A) {
 #pragma unroll
         for (int i4 = 0; i4 < 4; ++i4) {
           const int r = 16 * t + PR::crow(lane, i4);
-          if (r < L) sLD[i - 1][r * DS + col] += CD[t][i4];
+          if (r < L && col < NCL) sLD[i - 1][r * RL + col] += CD[t][i4];
         }
     }
     __syncthreads();
@@ -640,7 +664,7 @@ void k_adj_volume(AdjArgs<P> A) {
   for (int c = 0; c < NCH; ++c) {
     Acc C[4];
     zero_C<P, 4>(C);
-    wave_gemm<P, 4, KSL, DS>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
+    wave_gemm<P, 4, KSL, RL, KSL, NCL>(A.PTpk + (size_t)c * 4 * KSL * 64, sLD[1], C, lane);
     store_C<P, 4>(C, sX, 64, T(1), lane);
     __syncthreads();
     S.R_[64 * c + lane] = sX[lane * R + 9];
@@ -717,7 +741,10 @@ void k_adj_volume(AdjArgs<P> A) {
   __syncthreads();
   // lambda^n = (lambda^{n+1} + dJ/dD^0, held in sLD[0]) + nodal path
   T* out = A.lamOut + (size_t)e * KPL * 16;
-  for (int idx = lane; idx < KPL * DS; idx += 64) out[idx] = sLD[0][idx] + sZ[idx];
+  for (int idx = lane; idx < KPL * DS; idx += 64) {
+    const int o = lpos(idx);
+    out[idx] = (o >= 0 ? sLD[0][o] : T(0)) + sZ[idx];
+  }
   const T gm = wave_sum(gmu), gc = wave_sum(gcd);
   if (lane == 0) {
     double gf = 0.0;

@@ -961,8 +961,20 @@ void k_volume3(StepArgs<P> a) {
 // both sides at the shared face points for every time point, LLF (or
 // boundary) flux with the normal of the face's first element, time quadrature.
 // Writes sum_z gamma_z F*(t_z) at the Ns face points, [face][Ns][10].
+// Trace contractions of the face kernel with each trace-matrix fragment shared
+// by all time points (FP32 accumulators: 40 registers per side at degree 4).
+template <int P> struct FaceSharedA {
+  static constexpr bool value = P != PREC_F64;
+};
+
+// Degree 4 (c5 step, ms): FP32 faces 56.7 with the odd trace stride 11 at 3
+// wavefronts per SIMD against 57.9 with stride 10 at 4 (LDS within a
+// sixteenth of the compute unit's); split-BF16 faces 46.8 with stride 10 at 4
+// against 50.0.
 template <int N, int P> struct FaceWaves {
-  static constexpr int value = N >= 4 ? (P == PREC_F64 ? 2 : 3) : (P == PREC_F64 ? 4 : 7);
+  static constexpr int value =
+      N >= 4 ? (P == PREC_F64 ? 2 : (P == PREC_BF16 ? 4 : 3)) : (P == PREC_F64 ? 4 : 7);
+  static constexpr int stride = N >= 4 && P == PREC_BF16 ? 10 : 11;
 };
 
 template <int N, int P, class LW = CdmLaw>
@@ -977,7 +989,7 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   constexpr int KS = PR::KS, KPL = round_up(L, KS), KSL = KPL / KS;
   // traces keep only the 10 quantities: an odd row stride reads one row per
   // lane without bank conflicts and halves the LDS of the 16-column layout
-  constexpr int R = 11;
+  constexpr int R = FaceWaves<N, P>::stride;
   constexpr int TS = Ns * R;            // rows beyond Ns are never stored
   __shared__ T sTm[Nt * TS];
   __shared__ T sTp[Nt * TS];
@@ -993,9 +1005,6 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   const int kind = conn_kind(w), sp = conn_perm(w);
   const Law<T> law{a.amax, a.smin};
   const MatP<T> m = load_mat<T>(a.mat + e * 8);
-  // both sides' traces in one pass, so that the loads of both time-point
-  // states are in flight together (a boundary face evaluates its own side
-  // twice and uses the first)
   const bool inner = kind == 0;
   const long long nb = inner ? (long long)(of >> 2) : e;
   const int nf = inner ? (of & 3) : f, sq = inner ? conn_nperm(w) : sp;
@@ -1003,15 +1012,33 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
   const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
   const typename PR::AF* Fn = a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64;
+  if constexpr (FaceSharedA<P>::value) {
+    // one side after the other, all time points together: each trace-matrix
+    // fragment is loaded once per side instead of once per time point (a
+    // boundary face evaluates its own side twice and uses the first)
+    Acc C[Nt][NST];
 #pragma unroll
-  for (int z = 0; z < Nt; ++z) {
-    Acc C[NST], Cn[NST];
-    zero_C<P, NST>(C);
-    zero_C<P, NST>(Cn);
-    wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
-    wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, Cn, lane);
-    store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
-    store_C<P, NST, R, 10>(Cn, sTp + z * TS, Ns, T(1), lane);
+    for (int side = 0; side < 2; ++side) {
+#pragma unroll
+      for (int z = 0; z < Nt; ++z) zero_C<P, NST>(C[z]);
+      wave_gemm_shared_a<P, NST, KSL, Nt, 16, KPL * 16>(side ? Fn : Fe, side ? Uzn : Uze, C, lane);
+#pragma unroll
+      for (int z = 0; z < Nt; ++z)
+        store_C<P, NST, R, 10>(C[z], (side ? sTp : sTm) + z * TS, Ns, T(1), lane);
+    }
+  } else {
+    // both sides' traces in one pass, so that the loads of both time-point
+    // states are in flight together
+#pragma unroll
+    for (int z = 0; z < Nt; ++z) {
+      Acc C[NST], Cn[NST];
+      zero_C<P, NST>(C);
+      zero_C<P, NST>(Cn);
+      wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
+      wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, Cn, lane);
+      store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
+      store_C<P, NST, R, 10>(Cn, sTp + z * TS, Ns, T(1), lane);
+    }
   }
   __syncthreads();
   T n[3];

@@ -171,6 +171,27 @@ __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
   }
 }
 
+// C[z] += A x B_z for NZ matrices B_z = B + z BSTRIDE ([K][RS] each) that share
+// the packed A: every A fragment is loaded once for all of them.
+template <int P, int MT, int KSTEPS, int NZ, int RS, int BSTRIDE>
+__device__ inline void wave_gemm_shared_a(const typename Prec<P>::AF* __restrict__ Apk,
+                                          const typename Prec<P>::T* B,
+                                          typename Prec<P>::Acc (&C)[NZ][MT], int lane) {
+  using PR = Prec<P>;
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    typename PR::AF b[NZ];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) b[z] = PR::template loadB<RS>(B + z * BSTRIDE, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const typename PR::AF av = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) C[z][t] = PR::mma(av, b[z], C[z][t]);
+    }
+  }
+}
+
 // As wave_gemm, one output tile after the other (each B fragment is read once
 // per tile): fewer A fragments in flight, for kernels short of registers.
 template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS>
