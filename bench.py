@@ -280,10 +280,11 @@ def fd_check(w, steps, grads, nelem, seed=31):
             fd = (jp - jm) / (2 * h)
             # a difference of the misfit below ~1e-12 of the misfit itself is
             # rounding of the FP64 runs, not a derivative
-            rows.append({"param": which, "element": e, "adjoint": float(g[e]), "fd": fd,
-                         "rel_diff": abs(float(g[e]) - fd) / max(abs(fd), 1e-300),
-                         "misfit": j0, "adjoint_delta_misfit": abs(float(g[e])) * 2 * h,
-                         "resolved": abs(float(g[e])) * 2 * h > 1e-12 * abs(j0)})
+            dj = abs(float(g[e])) * 2 * float(h)
+            rows.append({"param": which, "element": e, "adjoint": float(g[e]), "fd": float(fd),
+                         "rel_diff": abs(float(g[e]) - float(fd)) / max(abs(float(fd)), 1e-300),
+                         "misfit": float(j0), "adjoint_delta_misfit": dj,
+                         "resolved": bool(dj > 1e-12 * abs(float(j0)))})
             print(f"fd check: {rows[-1]}", file=sys.stderr, flush=True)
     sim.close()
     return rows
@@ -509,12 +510,15 @@ def main():
                     help="precisions whose checkpointed adjoint is timed on the step workload "
                          "('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
-    ap.add_argument("--adjoint-runs", default="c4:400:20,c3:200:20",
-                    help="checkpointed FP32 adjoint runs workload:steps:every ('' for none)")
+    ap.add_argument("--adjoint-runs", default="c4:400:20,c3:200:20,c3:200:20:bf16",
+                    help="checkpointed adjoint runs workload:steps:every[:bf16] (FP32 "
+                         "adjoint arithmetic; bf16: split-BF16 forward) ('' for none)")
     ap.add_argument("--adjoint-fd", type=int, default=0,
                     help="central differences on this many elements for the last adjoint run")
     ap.add_argument("--ivm-precisions", default="fp32",
                     help="precisions of the IVM-rheology step timing ('' for none)")
+    ap.add_argument("--lts-workloads", default="c5f",
+                    help="further workloads timed with local time stepping ('' for none)")
     ap.add_argument("--lts-macro-steps", type=int, default=3,
                     help="macro steps of the local-time-stepping timing (0 for none)")
     ap.add_argument("--picard-steps", type=int, default=3,
@@ -599,6 +603,17 @@ def main():
     if args.lts_macro_steps > 0:
         line["lts"] = run_lts(w, main_prec, args.lts_macro_steps, res[main_prec]["ms_per_step"])
         print(f"lts: {line['lts']}", file=sys.stderr, flush=True)
+        for name in [q.strip() for q in args.lts_workloads.split(",") if q.strip()]:
+            # a mesh where part of the elements limits the global step (c5f:
+            # the c5 recipe with a band of layers 8 times thinner around the
+            # fault): global step and local time stepping on the same mesh
+            wl = make_workload(name)
+            g = run_precision(wl, main_prec, 3, 1, want_state=False)
+            ent = run_lts(wl, main_prec, args.lts_macro_steps, g["ms_per_step"])
+            ent["workload"] = f"{name}: {wl.ne} tets, N={wl.N}, global step {wl.dt:.3e} s"
+            ent["global_step_ms"] = g["ms_per_step"]
+            line[f"lts_{name}"] = ent
+            print(f"lts {name}: {ent}", file=sys.stderr, flush=True)
     if args.picard_steps > 0:
         line["picard"] = run_picard(w, main_prec, args.picard_steps, 1)
         print(f"picard: {line['picard']}", file=sys.stderr, flush=True)
@@ -616,17 +631,21 @@ def main():
         print(f"adjoint {p}: {a}", file=sys.stderr, flush=True)
         line[f"adjoint_{p}"] = a
     runs = [r.split(":") for r in args.adjoint_runs.split(",") if r.strip()]
-    for i, (name, steps, every) in enumerate(runs):
+    for i, spec in enumerate(runs):
+        name, steps, every = spec[:3]
+        aprec = spec[3] if len(spec) > 3 else "fp32"   # forward form; bf16: FP32 adjoint
         # checkpointed FP32 misfit gradient (mu0, C_d) against a run with the
         # perturbed model: c4 is the differentiation-form workload (82,944
         # tets, N=3, point source, 16 receivers, 400 steps, checkpoints every
         # 20), c3 the degree-4 precision-form mesh (1,572,864 tets)
         wa = make_workload(name)
-        a, grads = run_adjoint(wa, "fp32", int(steps), int(every), observed=True)
+        a, grads = run_adjoint(wa, aprec, int(steps), int(every), observed=True)
+        if aprec == "bf16":
+            a["arithmetic"] = "split-BF16 forward, FP32 adjoint"
         if args.adjoint_fd and i == len(runs) - 1:
             a["fd_check"] = fd_check(wa, int(steps), grads, args.adjoint_fd)
-        print(f"adjoint {name} fp32: {a}", file=sys.stderr, flush=True)
-        line[f"adjoint_{name}_fp32"] = a
+        print(f"adjoint {name} {aprec}: {a}", file=sys.stderr, flush=True)
+        line[f"adjoint_{name}_{aprec}"] = a
     if args.error_workload:
         eprecs = [q.strip() for q in args.error_precisions.split(",") if q.strip()]
         line["precision_errors"] = precision_errors(args.error_workload, args.error_steps, eprecs)

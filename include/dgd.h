@@ -357,8 +357,11 @@ dgd_status dgd_get_time_point_states(dgd_handle* h, double* out);
  * derivative where they are switched off (xi <= xi0, sqrt(I2) <= 1e-15); at a
  * tie of the two sides' Lax-Friedrichs speeds (Eq. rusanov-flux) each side
  * takes half of the derivative.  Point sources do not depend on the state or
- * on mu0, C_d.  Runs in FP64 or FP32 (DGD_BF16 handles return DGD_EINVAL); the
- * adjoint arithmetic has the handle's precision.  CDM law only.
+ * on mu0, C_d.  The adjoint arithmetic is FP64 on DGD_FP64 handles and FP32
+ * on the others: a DGD_BF16 handle runs its forward (and replayed) steps in
+ * its split-BF16 form and differentiates them with the FP32 adjoint of the
+ * step, taken at the states of that trajectory (its FP32 operators are
+ * packed on the first adjoint call).  CDM law only.
  *
  * dgd_adjoint_step: one reverse step on the device, asynchronous on the
  * solver's stream.  state_n: U^n, device [ne][10][L] FP64 (borrowed).

@@ -112,6 +112,8 @@ struct dgd_handle {
   // profiling: event pairs per kernel class
   // discrete adjoint: transposed reference data, adjoint state, checkpoints
   DevBuf VTpk, STpk, PTpk, KTpk;
+  // FP32 forward operators of a split-BF16 handle, for its FP32 adjoint
+  DevBuf Vpk32, Kpk32, Spk32, Fpk32, Lpk32, Ppk32, KPpk32;
   DevBuf lam[2], gtr, gmuf, lzf, gmu, gcd, adjW9, adjWa, dlds, seg9, sega, seguz, segd, segacc, save9, savea;
   DevBuf st9, sta;               // the state U^n handed to dgd_adjoint_step, working precision
   void* uz_override = nullptr;   // time-point states of the step being replayed
@@ -133,7 +135,8 @@ struct dgd_handle {
                      &s_elem, &s_M6, &s_dphi, &s_onset, &s_param, &s_rhoJ, &r_elem, &r_phi, &seis,
                      &VTpk, &STpk, &PTpk, &KTpk, &lam[0], &lam[1], &gtr, &gmuf, &lzf, &gmu, &gcd, &adjW9,
                      &adjWa, &dlds, &seg9, &sega, &seguz, &segd, &segacc, &save9, &savea, &st9, &sta,
-                     &KPpk, &ecl, &Dall, &facc};
+                     &KPpk, &ecl, &Dall, &facc, &Vpk32, &Kpk32, &Spk32, &Fpk32, &Lpk32, &Ppk32,
+                     &KPpk32};
     for (DevBuf* b : all) b->release();
     for (DevBuf& b : ck9) b.release();
     for (DevBuf& b : cka) b.release();
@@ -656,11 +659,40 @@ template <int N, int P> struct PredictFn {
 };
 
 // ---------------------------------------------------------------- discrete adjoint
-size_t lam_elems(const dgd_handle* h) { return (size_t)h->ne * h->kpl * 16; }
+// The adjoint arithmetic is FP64 on FP64 handles and FP32 on the others (a
+// split-BF16 handle runs its forward steps in that form and their adjoint in
+// FP32, at the states of its own trajectory): mode rows of the adjoint
+// states padded to the FP32/FP64 matrix-core k-step.
+int adj_kpl(const dgd_handle* h) { return round_up(h->ref.L, 4); }
+size_t lam_elems(const dgd_handle* h) { return (size_t)h->ne * adj_kpl(h) * 16; }
+
+// FP32 forward operators of a split-BF16 handle (its own packs hold BF16
+// hi/lo pairs), packed once beside them; the transposed adjoint operators
+// come with them.
+dgd_status ensure_adjoint_packs(dgd_handle* h) {
+  if (h->prec != DGD_BF16 || h->Vpk32.p) return DGD_OK;
+  DevBuf* fw[] = {&h->Vpk, &h->Kpk, &h->Spk, &h->Fpk, &h->Lpk, &h->Ppk, &h->KPpk};
+  DevBuf* f32[] = {&h->Vpk32, &h->Kpk32, &h->Spk32, &h->Fpk32, &h->Lpk32, &h->Ppk32, &h->KPpk32};
+  for (int i = 0; i < 7; ++i) std::swap(*fw[i], *f32[i]);
+  const int kpl = h->kpl;
+  dgd_status s = DGD_EINVAL;
+  switch (h->N) {
+    case 1: s = build_packed<1, PREC_F32>(h); break;
+    case 2: s = build_packed<2, PREC_F32>(h); break;
+    case 3: s = build_packed<3, PREC_F32>(h); break;
+    case 4: s = build_packed<4, PREC_F32>(h); break;
+    default: break;
+  }
+  h->kpl = kpl;
+  for (int i = 0; i < 7; ++i) std::swap(*fw[i], *f32[i]);
+  if (s) h->Vpk32.release();
+  return s;
+}
 
 dgd_status alloc_adjoint(dgd_handle* h) {
   const size_t E = (size_t)h->ne, L = h->ref.L;
   dgd_status s;
+  if ((s = ensure_adjoint_packs(h))) return s;
   if ((s = dalloc(h, h->lam[0], lam_elems(h) * h->tsize)) ||
       (s = dalloc(h, h->lam[1], lam_elems(h) * h->tsize)) ||
       (s = dalloc(h, h->gtr, (size_t)h->nfaces * 2 * h->ref.Nt * h->ref.Ns * 10 * h->tsize)) ||
@@ -684,11 +716,25 @@ dgd_status adjoint_step_impl(dgd_handle* h, const void* U9, const double* Ua, co
   using T = typename Prec<P>::T;
   using AF = typename Prec<P>::AF;
   if constexpr (P == PREC_BF16) {
-    return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
+    // split-BF16 forward: the adjoint arithmetic is FP32
+    return adjoint_step_impl<N, PREC_F32>(h, U9, Ua, lam_in, lam_out, uz, dk, ak, gmu, gcd);
   } else {
     const long long per = (h->ne + 7) / 8;
     const dim3 grid((unsigned)(8 * per)), block(64);
     StepArgs<P> a = make_args<N, P>(h);
+    if (h->prec == DGD_BF16) {
+      // the FP32 operators packed beside the handle's BF16 ones; the
+      // time-point states are recomputed in FP32 (uz, dk, ak are null)
+      if (uz || dk || ak) return fail(h, DGD_EINVAL, "kept BF16 predictions in an FP32 adjoint");
+      a.Vpk = (const AF*)h->Vpk32.p;
+      a.Kpk = (const AF*)h->Kpk32.p;
+      a.Spk = (const AF*)h->Spk32.p;
+      a.Fpk = (const AF*)h->Fpk32.p;
+      a.Lpk = (const AF*)h->Lpk32.p;
+      a.Ppk = (const typename Prec<Accurate<P>::value>::AF*)h->Ppk32.p;
+      a.Dkeep = nullptr;
+      a.Akeep = nullptr;
+    }
     a.Uz = (T*)(uz ? uz : h->Uz.p);
     a.U9 = (const T*)U9;
     a.Ua = Ua;
@@ -745,14 +791,14 @@ template <class T>
 void launch_lam_from_f64(dgd_handle* h, const double* src, void* lam) {
   const long long n = (long long)lam_elems(h);
   hipLaunchKernelGGL((k_lam_from_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     h->stream, h->ne, h->ref.L, h->kpl, src, (T*)lam);
+                     h->stream, h->ne, h->ref.L, adj_kpl(h), src, (T*)lam);
 }
 
 template <class T>
 void launch_lam_to_f64(dgd_handle* h, const void* lam, double* dst) {
   const long long n = h->ne * 10 * h->ref.L;
   hipLaunchKernelGGL((k_lam_to_f64<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
-                     h->ne, h->ref.L, h->kpl, (const T*)lam, dst);
+                     h->ne, h->ref.L, adj_kpl(h), (const T*)lam, dst);
 }
 
 void release_tape(dgd_handle* h) {
@@ -1734,7 +1780,6 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* state_n, double* lam,
                             const double* dJ_dseis_n, double* grad_mu0, double* grad_cd) {
   if (!h) return DGD_EINVAL;
   if (!state_n || !lam) return fail(h, DGD_EINVAL, "null state or adjoint state");
-  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
   if (h->predictor != 0)
     return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
@@ -1759,11 +1804,11 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* state_n, double* lam,
   if (dJ_dseis_n && h->nrec > 0) {
     if (h->prec == DGD_FP64)
       hipLaunchKernelGGL((k_adj_receivers<double>), dim3(1), dim3(3 * L), 0, h->stream, h->nrec,
-                         (int)L, h->kpl, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                         (int)L, adj_kpl(h), (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
                          dJ_dseis_n, (double*)h->lam[0].p);
     else
       hipLaunchKernelGGL((k_adj_receivers<float>), dim3(1), dim3(3 * L), 0, h->stream, h->nrec,
-                         (int)L, h->kpl, (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
+                         (int)L, adj_kpl(h), (const long long*)h->r_elem.p, (const double*)h->r_phi.p,
                          dJ_dseis_n, (float*)h->lam[0].p);
   }
   HIPCHK(h, hipGetLastError());
@@ -1783,7 +1828,6 @@ dgd_status dgd_adjoint_step(dgd_handle* h, const double* state_n, double* lam,
 dgd_status dgd_adjoint_step_host(dgd_handle* h, const double* lam_next, double* lam_out,
                                  double* grad_mu0, double* grad_cd) {
   if (!h || !lam_next || !lam_out) return DGD_EINVAL;
-  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
   if (h->predictor != 0)
     return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
@@ -1826,7 +1870,6 @@ dgd_status dgd_adjoint_step_host(dgd_handle* h, const double* lam_next, double* 
 dgd_status dgd_forward_checkpointed(dgd_handle* h, int64_t nsteps, int64_t every) {
   if (!h) return DGD_EINVAL;
   if (nsteps < 1 || every < 1) return fail(h, DGD_EINVAL, "nsteps >= 1 and every >= 1 needed");
-  if (h->prec == DGD_BF16) return fail(h, DGD_EINVAL, "the adjoint runs in FP64 or FP32");
   if (h->law != 0) return fail(h, DGD_EINVAL, "the adjoint is that of the continuum-damage law");
   if (h->predictor != 0)
     return fail(h, DGD_EINVAL, "the adjoint is that of the Cauchy-Kovalevskaya predictor");
@@ -1880,9 +1923,11 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
       (s = dalloc(h, h->sega, (size_t)every * E * L * sizeof(double))))
     return s;
   // time-point states of every step of a segment, kept from the replay so
-  // that the adjoint need not recompute them (skipped if memory is short)
+  // that the adjoint need not recompute them (skipped if memory is short,
+  // and under a split-BF16 forward, whose predictions are not the FP32
+  // adjoint's)
   const size_t uzb = E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize;
-  bool keep_uz = dalloc(h, h->seguz, (size_t)every * uzb) == DGD_OK;
+  bool keep_uz = h->prec != DGD_BF16 && dalloc(h, h->seguz, (size_t)every * uzb) == DGD_OK;
   if (!keep_uz) {
     (void)hipGetLastError();
     h->err.clear();
@@ -1939,11 +1984,11 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
         timed(h, 7, [&] {
           if (h->prec == DGD_FP64)
             hipLaunchKernelGGL((k_adj_receivers<double>), dim3(1), dim3(3 * L), 0, h->stream, nrec,
-                               (int)L, h->kpl, (const long long*)h->r_elem.p,
+                               (int)L, adj_kpl(h), (const long long*)h->r_elem.p,
                                (const double*)h->r_phi.p, g, (double*)h->lam[lc].p);
           else
             hipLaunchKernelGGL((k_adj_receivers<float>), dim3(1), dim3(3 * L), 0, h->stream, nrec,
-                               (int)L, h->kpl, (const long long*)h->r_elem.p,
+                               (int)L, adj_kpl(h), (const long long*)h->r_elem.p,
                                (const double*)h->r_phi.p, g, (float*)h->lam[lc].p);
         });
       }
