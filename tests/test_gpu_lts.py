@@ -6,8 +6,9 @@ dgd_make_clusters, dgd_step_lts) against the oracle's (oracle/lts.py).
   from the per-element admissible steps (soft basin over rock).
 * Macro steps with several clusters match the oracle per quantity group
   (relative L2, pointwise maximum, per element): the periodic basin with its
-  clusters from the wave speeds, and a bounded mesh with damage growth and a
-  clustered half; FP64 1e-10, FP32 1e-5, BF16 3e-3.
+  clusters from the wave speeds, a bounded mesh with damage growth and a
+  clustered half, and a mesh graded in depth around a fault (clusters from
+  the element sizes); FP64 1e-10, FP32 1e-5, BF16 3e-3.
 * The wave quantities are conserved across cluster boundaries on the device.
 * A point source (the c4 double couple, Ricker moment rate) in a clustered
   mesh, with receivers: state and seismograms against the oracle.
@@ -68,23 +69,51 @@ def _half(w):
 
 CASES = [
     # periodic basin, clusters from the wave speeds
-    ("basin", dict(n=4, N=2, periodic=True), 2),
+    ("basin", "c2", dict(n=4, N=2, periodic=True), 2),
     # bounded basin with damage growth, x < l/2 at twice the step
-    ("half", dict(n=3, N=3), 2),
+    ("half", "c2", dict(n=3, N=3), 2),
+    # the mesh graded in depth around a fault (a band of layers 8 times
+    # thinner), clusters from the element sizes and wave speeds, a plane P
+    # wave through it
+    ("band", "c5f", dict(n=6, N=2), 1),
 ]
 
 
+def _band_workload(w):
+    from workloads import plane_wave_ic
+    w.sources = None
+    w.receivers = None
+    w.ic = plane_wave_ic(w.mesh["length"], 1e-5, 6000.0)
+    return w
+
+
+_ORACLE = {}
+
+
+def _oracle_case(kind, name, kw, nmacro):
+    """Workload, clusters, initial and final oracle states of a case (the
+    oracle's run is shared by the precisions)."""
+    key = (kind, name, tuple(sorted(kw.items())), nmacro)
+    if key not in _ORACLE:
+        w = make_workload(name, **kw)
+        if kind == "band":
+            w = _band_workload(w)
+        S = oracle_from(w)
+        if kind in ("basin", "band"):
+            cl, dt0 = make_clusters(admissible_steps(S), S.mesh.nbr, 8 if kind == "band" else 3)
+        else:
+            cl, dt0 = _half(w), w.dt / 2
+        U0 = S.project(w.ic)
+        _ORACLE[key] = (w, cl, dt0, U0, LtsSolver(S, cl, dt0).run(U0, nmacro))
+    return _ORACLE[key]
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16", 3e-3)])
-@pytest.mark.parametrize("kind,kw,nmacro", CASES)
-def test_lts_parity(kind, kw, nmacro, prec, tol):
-    w = make_workload("c2", **kw)
-    S = oracle_from(w)
-    if kind == "basin":
-        cl, dt0 = make_clusters(admissible_steps(S), S.mesh.nbr, 3)
-    else:
-        cl, dt0 = _half(w), w.dt / 2
-    U0 = S.project(w.ic)
-    want = LtsSolver(S, cl, dt0).run(U0, nmacro)
+@pytest.mark.parametrize("kind,name,kw,nmacro", CASES)
+def test_lts_parity(kind, name, kw, nmacro, prec, tol):
+    w, cl, dt0, U0, want = _oracle_case(kind, name, kw, nmacro)
+    if kind == "band":
+        assert cl.max() >= 2 and (cl == 0).any()
     sim = _api().from_workload(w, prec, state=False)
     sim.set_state(_to_lib(U0))
     sim.set_clusters(cl, dt0)

@@ -117,3 +117,27 @@ def test_plane_wave_with_a_clustered_half():
     print(f"LTS {e3:.3e} (global step {g3:.3e}), refined {e6:.3e}, order {rate:.2f}")
     assert abs(e3 - g3) <= 0.1 * g3
     assert rate >= N + 0.5
+
+
+def test_clusters_of_a_mesh_graded_around_a_fault():
+    """The c5 recipe on a mesh whose band of layers around the fault is 8 times
+    thinner: the band takes the smallest step, the coarse rock above and below
+    at least twice it, and the global rule of the workload is the band's."""
+    w = make_workload("c5f", n=12, N=2)
+    S = oracle_from(w)
+    assert bool((S.mesh.detJ > 0).all())
+    z = w.mesh["z_nodes"]
+    dz = np.diff(z)
+    thin = dz < 0.5 * dz.max()
+    assert thin.sum() == 2 and abs(dz[thin][0] * 8 - dz.max()) < 1e-9 * dz.max()
+    dte = admissible_steps(S)
+    cl, dt0 = make_clusters(dte, S.mesh.nbr, 8)
+    assert abs(dt0 - w.dt) < 1e-12 * w.dt
+    cent = w.mesh["xyz"][w.mesh["tets"]].mean(axis=1)[:, 2]
+    band = (cent > z[:-1][thin].min()) & (cent < z[1:][thin].max())
+    assert np.all(cl[band] == 0)
+    # coarse elements with no band neighbour step at least twice as long
+    nb = S.mesh.nbr
+    touches = np.array([band[nb[e][nb[e] >= 0]].any() for e in range(S.E)])
+    assert np.all(cl[~band & ~touches] >= 1)
+    assert np.all(dt0 * 2.0 ** cl <= dte * (1 + 1e-12))

@@ -25,6 +25,10 @@ Workload recipe (seeds: 0 initial condition and material, 1 source,
 * ``c5`` [0,24 km]^3, 96^3 cubes, N=4, a 3 km basin whose vs rises linearly
   from 300 m/s at the surface to 2000 m/s, 64 subfault point sources on a
   30-degree dipping plane; 2000 steps.
+* ``c5f`` c5 on a mesh graded in depth: 16 of the 96 layers, 8 times thinner
+  than the others, form a band centred on the fault (6 km deep), as a mesh
+  refined around a fault would; its global step is that band's (the
+  workload for local time stepping).
 
 ``rheology="ivm"`` keeps any recipe's mesh, elastic model, initial condition
 and sources and gives the IVM law its parameters: gamma_b = 0.5 kPa in
@@ -40,7 +44,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from .mesh import cube_mesh, kuhn_inradius
+from .mesh import cube_mesh, kuhn_inradius, tet_inradius
 
 ALPHA_MAX = 0.5
 CFL = 0.5
@@ -84,10 +88,32 @@ class Workload:
 
 
 def cfl_dt(mesh, material, N, cfl=CFL):
-    """Global step from the intact moduli: cfl * 2 r_in / ((2N+1) c_p,max)."""
+    """Global step from the intact moduli: cfl * 2 r_in / ((2N+1) c_p,max) on
+    a uniform mesh; on a graded one the smallest cfl * 2 r_in,e / ((2N+1) c_p,e)
+    over the elements."""
     cp = np.sqrt((material["lambda0"] + 2.0 * material["mu0"]) / material["rho"])
-    r_in = kuhn_inradius(mesh["edge"])
-    return cfl * 2.0 * r_in / ((2 * N + 1) * float(cp.max()))
+    if mesh.get("z_nodes") is None:
+        r_in = kuhn_inradius(mesh["edge"])
+        return cfl * 2.0 * r_in / ((2 * N + 1) * float(cp.max()))
+    r = tet_inradius(mesh["xyz"], mesh["tets"])
+    return cfl * 2.0 * float(np.min(r / cp)) / (2 * N + 1)
+
+
+def fault_band_nodes(n, length, centre_depth=6000.0, factor=8):
+    """Node heights of n layers: a band of max(1, n // 6) layers, `factor`
+    times thinner than the others, centred `centre_depth` below the top (a
+    mesh refined around a fault); the other layers share the rest equally."""
+    m = max(1, n // 6)
+    zc = length - centre_depth
+    a = length / (n - m + m / factor)             # coarse spacing
+    k1 = int(round((zc - 0.5 * m * a / factor) / a))
+    k1 = min(max(k1, 0), n - m)
+    k2 = n - m - k1
+    a = length / (k1 + k2 + m / factor)
+    steps = [a] * k1 + [a / factor] * m + [a] * k2
+    z = np.concatenate([[0.0], np.cumsum(steps)])
+    z[-1] = length
+    return z
 
 
 def _centroids(mesh):
@@ -250,6 +276,8 @@ CONFIGS = {
     "c3": dict(n=64, length=1000.0, N=4, nsteps=1000),
     "c4": dict(n=24, length=24000.0, N=3, nsteps=400),
     "c5": dict(n=96, length=24000.0, N=4, nsteps=2000),
+    # c5 on a mesh refined 8x in depth around the fault (for local time stepping)
+    "c5f": dict(n=96, length=24000.0, N=4, nsteps=2000),
 }
 
 
@@ -295,7 +323,8 @@ def _make(name, n, N, nsteps, seed, periodic):
         wl.extra["cp"] = cp
         wl.extra["amplitude"] = 1e-6
         return wl
-    mesh = cube_mesh(n, ell, periodic=bool(periodic))
+    zn = fault_band_nodes(n, ell) if name == "c5f" else None
+    mesh = cube_mesh(n, ell, periodic=bool(periodic), z_nodes=zn)
     ne = mesh["tets"].shape[0]
     if name in ("c2", "c3", "c4"):
         mat = _layered(mesh)
@@ -328,7 +357,7 @@ def _make(name, n, N, nsteps, seed, periodic):
                           t_onset=np.array([1.2 / f0]), stf_param=np.array([f0]),
                           stf_kind=STF_RICKER)
         wl.receivers = _receivers_top(mesh)
-    if name == "c5":
+    if name in ("c5", "c5f"):
         wl.sources = _finite_fault(mesh, src_rng, 3.24e10)
         wl.receivers = _receivers_top(mesh)
     return wl

@@ -38,13 +38,16 @@ def kuhn_inradius(edge):
 
 
 def cube_mesh(n, length, periodic=False, origin=(0.0, 0.0, 0.0),
-              top_free=True):
+              top_free=True, z_nodes=None):
     """Return a dict with ``xyz`` (nv,3) f64, ``tets`` (ne,4) i64,
     ``face_tag`` (ne,4) i8, ``periodic_map`` (nv,) i64 or None, ``n``,
-    ``length`` and ``edge``.
+    ``length``, ``edge`` (the uniform spacing) and ``z_nodes``.
 
     Non-periodic meshes tag the top face z = origin_z + length as free surface
     (if ``top_free``) and the other five domain faces as absorbing.
+    ``z_nodes`` (n+1 increasing heights from 0 to ``length``) replaces the
+    uniform spacing along z: a mesh graded in depth (boxes instead of cubes,
+    still split into six positively oriented tetrahedra); not periodic.
     """
     n = int(n)
     h = float(length) / n
@@ -54,6 +57,12 @@ def cube_mesh(n, length, periodic=False, origin=(0.0, 0.0, 0.0),
     kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
     ijk = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
     xyz = o[None, :] + h * ijk.astype(np.float64)
+    if z_nodes is not None:
+        z = np.asarray(z_nodes, dtype=np.float64)
+        if periodic or z.shape != (n + 1,) or not np.all(np.diff(z) > 0) \
+                or abs(z[0]) > 1e-9 * length or abs(z[-1] - length) > 1e-9 * length:
+            raise ValueError("z_nodes: n+1 increasing heights from 0 to length, not periodic")
+        xyz[:, 2] = o[2] + z[ijk[:, 2]]
 
     def vid(i, j, k):
         return i + (n + 1) * (j + (n + 1) * k)
@@ -95,4 +104,17 @@ def cube_mesh(n, length, periodic=False, origin=(0.0, 0.0, 0.0),
                 else:
                     face_tag[on_hi, f] = TAG_ABSORB
     return {"xyz": xyz, "tets": tets, "face_tag": face_tag,
-            "periodic_map": pm, "n": n, "length": float(length), "edge": h}
+            "periodic_map": pm, "n": n, "length": float(length), "edge": h,
+            "z_nodes": None if z_nodes is None else np.asarray(z_nodes, dtype=np.float64)}
+
+
+def tet_inradius(xyz, tets):
+    """Inradius 3V/A of every tetrahedron (volume over total face area)."""
+    X = xyz[tets]                                              # (ne, 4, 3)
+    vol = np.abs(np.einsum("ei,ei->e", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]),
+                           X[:, 3] - X[:, 0])) / 6.0
+    area = np.zeros(len(tets))
+    for fv in FACE_VERTS:
+        a, b, c = X[:, fv[0]], X[:, fv[1]], X[:, fv[2]]
+        area += 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    return 3.0 * vol / area
