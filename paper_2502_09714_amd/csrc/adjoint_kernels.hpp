@@ -88,18 +88,21 @@ void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
   const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
   const typename PR::AF* Fn =
       a.Fpk + (size_t)(nf * 6 + (inner ? conn_nperm(w) : sp)) * NST * KSL * 64;
-  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
-  const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+  const T* Uze = a.Uz + (size_t)e * DM::UZE;
+  const T* Uzn = a.Uz + (size_t)nb * DM::UZE;
 #pragma unroll
   for (int z = 0; z <= Nt; ++z) {
-    // z < Nt: time-point states; z = Nt: lambda^{n+1}
-    const T* Be = z < Nt ? Uze + z * KPL * 16 : A.lam + (size_t)e * KPL * 16;
-    const T* Bn = z < Nt ? Uzn + z * KPL * 16 : A.lam + (size_t)nb * KPL * 16;
+    // z < Nt: time-point states ([L][10]); z = Nt: lambda^{n+1} ([KPL][16])
     Acc C[NST], Cn[NST];
     zero_C<P, NST>(C);
     zero_C<P, NST>(Cn);
-    wave_gemm<P, NST, KSL, 16>(Fe, Be, C, lane);
-    wave_gemm<P, NST, KSL, 16>(Fn, Bn, Cn, lane);
+    if (z < Nt) {
+      wave_gemm<P, NST, KSL, 10>(Fe, Uze + z * DM::UZT, C, lane);
+      wave_gemm<P, NST, KSL, 10>(Fn, Uzn + z * DM::UZT, Cn, lane);
+    } else {
+      wave_gemm<P, NST, KSL, 16>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
+      wave_gemm<P, NST, KSL, 16>(Fn, A.lam + (size_t)nb * KPL * 16, Cn, lane);
+    }
     store_C<P, NST, R, 10>(C, z < Nt ? sTm + z * TS : sLm, Ns, T(1), lane);
     store_C<P, NST, R, 10>(Cn, z < Nt ? sTp + z * TS : sLp, Ns, T(1), lane);
   }
@@ -326,11 +329,14 @@ void k_adj_points(AdjArgs<P> A) {
     __syncthreads();
   }
 
-  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
+  const T* Uze = a.Uz + (size_t)e * DM::UZE;
 #pragma unroll 1
   for (int z = 0; z < Nt; ++z) {
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) sZ[lane + 64 * j] = Uze[z * KPL * 16 + lane + 64 * j];
+    for (int j = 0; j < DPL; ++j) {
+      const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+      sZ[idx] = (l < L && p < 10) ? Uze[z * DM::UZT + l * 10 + p] : T(0);
+    }
     __syncthreads();
     const T g = a.gamma[z];
     Acc Cl[MT];

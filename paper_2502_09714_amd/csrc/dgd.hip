@@ -937,6 +937,22 @@ dgd_status ensure_seis(dgd_handle* h, long long extra) {
   return DGD_OK;
 }
 
+// bytes of the time-point states of all elements, [E][Nt][L][10], and of the
+// zeroed tail after them that the matrix cores' in-place reads of the last
+// element's padding rows reach (KPL * 16 entries)
+size_t uz_bytes(const dgd_handle* h) {
+  return (size_t)h->ne * h->ref.Nt * h->ref.L * 10 * h->tsize;
+}
+size_t uz_tail(const dgd_handle* h) { return (size_t)h->kpl * 16 * h->tsize; }
+
+// a buffer of `slots` consecutive time-point-state arrays and the zeroed tail
+dgd_status alloc_uz(dgd_handle* h, DevBuf& b, size_t slots) {
+  dgd_status s = dalloc(h, b, slots * uz_bytes(h) + uz_tail(h));
+  if (s) return s;
+  HIPCHK(h, hipMemsetAsync(b.p, 0, b.n, h->stream));
+  return DGD_OK;
+}
+
 dgd_status alloc_state(dgd_handle* h) {
   const size_t L = h->ref.L, E = (size_t)h->ne;
   dgd_status s;
@@ -944,7 +960,7 @@ dgd_status alloc_state(dgd_handle* h) {
     if ((s = dalloc(h, h->U9[i], E * 9 * L * h->tsize))) return s;
     if ((s = dalloc(h, h->Ua[i], E * L * sizeof(double)))) return s;
   }
-  if ((s = dalloc(h, h->Uz, E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize))) return s;
+  if ((s = alloc_uz(h, h->Uz, 1))) return s;
   if ((s = dalloc(h, h->fflux, (size_t)h->nfaces * h->ref.Ns * 10 * h->tsize))) return s;
   if ((s = dalloc(h, h->flag, sizeof(int)))) return s;
   HIPCHK(h, hipMemsetAsync(h->flag.p, 0, sizeof(int), h->stream));
@@ -1756,9 +1772,9 @@ dgd_status dgd_get_kernel_times(dgd_handle* h, double* ms, int64_t* launches) {
 dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
   if (!h || !out) return DGD_EINVAL;
   if (!h->have_state) return fail(h, DGD_ESTATE, "no state");
-  // device layout [e][z][l][16] (fragment layout, padded) -> [e][z][p][l]
-  const size_t L = h->ref.L, Nt = h->ref.Nt, K = (size_t)h->kpl;
-  const size_t n = (size_t)h->ne * Nt * K * 16;
+  // device layout [e][z][l][10] -> [e][z][p][l]
+  const size_t L = h->ref.L, Nt = h->ref.Nt;
+  const size_t n = (size_t)h->ne * Nt * L * 10;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   std::vector<double> tmp(n);
   if (h->prec == DGD_FP64) {
@@ -1772,7 +1788,7 @@ dgd_status dgd_get_time_point_states(dgd_handle* h, double* out) {
     for (size_t z = 0; z < Nt; ++z)
       for (size_t p = 0; p < 10; ++p)
         for (size_t l = 0; l < L; ++l)
-          out[((e * Nt + z) * 10 + p) * L + l] = tmp[((e * Nt + z) * K + l) * 16 + p];
+          out[((e * Nt + z) * 10 + p) * L + l] = tmp[((e * Nt + z) * L + l) * 10 + p];
   return DGD_OK;
 }
 
@@ -1926,8 +1942,8 @@ dgd_status dgd_backward(dgd_handle* h, const double* dl_dseis, double* grad_mu0,
   // that the adjoint need not recompute them (skipped if memory is short,
   // and under a split-BF16 forward, whose predictions are not the FP32
   // adjoint's)
-  const size_t uzb = E * h->ref.Nt * (size_t)h->kpl * 16 * h->tsize;
-  bool keep_uz = h->prec != DGD_BF16 && dalloc(h, h->seguz, (size_t)every * uzb) == DGD_OK;
+  const size_t uzb = uz_bytes(h);
+  bool keep_uz = h->prec != DGD_BF16 && alloc_uz(h, h->seguz, (size_t)every) == DGD_OK;
   if (!keep_uz) {
     (void)hipGetLastError();
     h->err.clear();

@@ -32,6 +32,10 @@ template <int N> struct Dims {
   static constexpr int NCH = (Q + 63) / 64;  // 64-point chunks of volume points
   static constexpr int MT = (L + 15) / 16;   // 16-row tiles of a mode-indexed output
   static constexpr int NST = (Ns + 15) / 16; // 16-row tiles of a face-point output
+  // time-point states in HBM, [E][Nt][L][10]: UZT values per time point,
+  // UZE per element (see StepArgs::Uz)
+  static constexpr int UZT = L * 10;
+  static constexpr int UZE = Nt * UZT;
 };
 
 // connectivity word: bits 0-1 face kind (0 interior, 1 free, 2 absorbing),
@@ -49,7 +53,13 @@ template <int P> struct StepArgs {
   const double* Ua;     // [E][L] current damage (FP64)
   T* W9;                // [E][9][L] next state
   double* Wa;           // [E][L]
-  T* Uz;                // [E][Nt][KPL][16] time-point states, fragment layout
+  // [E][Nt][L][10] time-point states, no padding.  The matrix cores read them
+  // in place as B operands with row stride 10: lanes of columns 10..15 read
+  // the next row's first entries and feed only output columns that are
+  // dropped, and the k-steps past row L (up to KPL) meet zero columns of the
+  // reference matrices; the allocation holds KPL * 16 zeroed entries past the
+  // last element so that those reads stay inside it and finite.
+  T* Uz;
   const double* geo;    // [E][16]: Theta^-1 (row e, column d), |J|
   const double* fgeo;   // [E][4][4]: outward normal, |S_f|/|J|
   const double* mat;    // [E][8]: rho, lambda0, mu0, gamma_r, xi0, C_d
@@ -398,8 +408,10 @@ template <int N, int P> struct PredWaves {
   static constexpr int value =
       !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : (P == PREC_BF16 ? 3 : 4)));
 };
+// (Split-BF16 volume at degree 4: 3 wavefronts per SIMD, where its 162
+// registers fit; at 4 the budget of 128 spills.)
 template <int N, int P> struct VolWaves {
-  static constexpr int value = P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 4 : 2));
+  static constexpr int value = P == PREC_F64 ? (N <= 3 ? 4 : 2) : (N <= 3 ? 6 : (P == PREC_BF16 ? 3 : 2));
 };
 
 // Prediction (Appendix A.1): Cauchy-Kovalevskaya derivatives of the element
@@ -443,7 +455,7 @@ void k_predict(StepArgs<P> a) {
       for (int j = 0; j < DPL; ++j) De[(i - 1) * KPL * 16 + lane + 64 * j] = Dv(i, j);
     if (a.Akeep && lane < 48) a.Akeep[e * 48 + lane] = S.Acc[lane];
   }
-  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+  T* Uzo = a.Uz + (size_t)e * DM::UZE;
 #pragma unroll
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
@@ -456,7 +468,8 @@ void k_predict(StepArgs<P> a) {
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * Dv(i, j);
-      Uzo[z * KPL * 16 + lane + 64 * j] = v;
+      const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+      if (l < L && p < 10) Uzo[z * DM::UZT + l * 10 + p] = v;
     }
   }
 }
@@ -605,11 +618,14 @@ void k_predict_picard(StepArgs<P> a, PicardArgs<P> pa) {
       for (int j = 0; j < DPL; ++j) S.Uz[z][lane + 64 * j] = un[z][j];
   }
   __syncthreads();
-  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+  T* Uzo = a.Uz + (size_t)e * DM::UZE;
 #pragma unroll
   for (int z = 0; z < Nt; ++z)
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) Uzo[z * KPL * 16 + lane + 64 * j] = S.Uz[z][lane + 64 * j];
+    for (int j = 0; j < DPL; ++j) {
+      const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+      if (l < L && p < 10) Uzo[z * DM::UZT + l * 10 + p] = S.Uz[z][idx];
+    }
 }
 
 // LDS of the volume half: nodal values / integrands of one 64-point chunk, the
@@ -656,13 +672,19 @@ void k_volume(StepArgs<P> a) {
   T Ji[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Ji[k] = (T)a.geo[e * 16 + k];
-  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
-  // time-point states go through LDS one at a time; the next one's loads are
-  // in flight while the current one is evaluated
-  constexpr int DPL = KPL * 16 / 64;
-  T nxt[DPL];
+  const T* Uze = a.Uz + (size_t)e * DM::UZE;
+  // time-point states go through LDS one at a time, into [l][16] with the
+  // padding rows and columns zero (set here, never written again); the next
+  // one's loads are in flight while the current one is evaluated
+  constexpr int ZPL = (DM::UZT + 63) / 64;
+  for (int i = lane; i < KPL * 16; i += 64) S.W[i] = T(0);
+  auto uz_at = [&](int z, int j) -> T {
+    const int idx = lane + 64 * j;
+    return idx < DM::UZT ? Uze[z * DM::UZT + idx] : T(0);
+  };
+  T nxt[ZPL];
 #pragma unroll
-  for (int j = 0; j < DPL; ++j) nxt[j] = Uze[lane + 64 * j];
+  for (int j = 0; j < ZPL; ++j) nxt[j] = uz_at(0, j);
 
   T vs[NCH][3], ss[NCH][6], sacc[NCH];
 #pragma unroll
@@ -676,10 +698,13 @@ void k_volume(StepArgs<P> a) {
   for (int z = 0; z < Nt; ++z) {
     const T g = a.gamma[z];
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) S.W[lane + 64 * j] = nxt[j];
+    for (int j = 0; j < ZPL; ++j) {
+      const int idx = lane + 64 * j;
+      if (idx < DM::UZT) S.W[(idx / 10) * 16 + idx % 10] = nxt[j];
+    }
     if (z + 1 < Nt) {
 #pragma unroll
-      for (int j = 0; j < DPL; ++j) nxt[j] = Uze[(z + 1) * KPL * 16 + lane + 64 * j];
+      for (int j = 0; j < ZPL; ++j) nxt[j] = uz_at(z + 1, j);
     }
     __syncthreads();
 #pragma unroll
@@ -852,11 +877,12 @@ void k_volume3(StepArgs<P> a) {
     // the three elements' time-point states, quantities side by side
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T* Uz = a.Uz + (size_t)(el[j] >= 0 ? el[j] : el[0]) * Nt * KPL * 16 + z * KPL * 16;
+      // (rows L..KPL-1 keep the zeros set at the start)
+      const T* Uz = a.Uz + (size_t)(el[j] >= 0 ? el[j] : el[0]) * DM::UZE + z * DM::UZT;
 #pragma unroll
-      for (int q = 0; q < DPL; ++q) {
-        const int idx = lane + 64 * q, l = idx >> 4, p = idx & 15;
-        if (p < 10) sW[l * RS + 10 * j + p] = el[j] >= 0 ? Uz[idx] : T(0);
+      for (int q = 0; q < (DM::UZT + 63) / 64; ++q) {
+        const int idx = lane + 64 * q;
+        if (idx < DM::UZT) sW[(idx / 10) * RS + 10 * j + idx % 10] = el[j] >= 0 ? Uz[idx] : T(0);
       }
     }
     __syncthreads();
@@ -1008,8 +1034,8 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
   const bool inner = kind == 0;
   const long long nb = inner ? (long long)(of >> 2) : e;
   const int nf = inner ? (of & 3) : f, sq = inner ? conn_nperm(w) : sp;
-  const T* Uze = a.Uz + (size_t)e * Nt * KPL * 16;
-  const T* Uzn = a.Uz + (size_t)nb * Nt * KPL * 16;
+  const T* Uze = a.Uz + (size_t)e * DM::UZE;
+  const T* Uzn = a.Uz + (size_t)nb * DM::UZE;
   const typename PR::AF* Fe = a.Fpk + (size_t)(f * 6 + sp) * NST * KSL * 64;
   const typename PR::AF* Fn = a.Fpk + (size_t)(nf * 6 + sq) * NST * KSL * 64;
   if constexpr (FaceSharedA<P>::value) {
@@ -1021,7 +1047,7 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
     for (int side = 0; side < 2; ++side) {
 #pragma unroll
       for (int z = 0; z < Nt; ++z) zero_C<P, NST>(C[z]);
-      wave_gemm_shared_a<P, NST, KSL, Nt, 16, KPL * 16>(side ? Fn : Fe, side ? Uzn : Uze, C, lane);
+      wave_gemm_shared_a<P, NST, KSL, Nt, 10, DM::UZT>(side ? Fn : Fe, side ? Uzn : Uze, C, lane);
 #pragma unroll
       for (int z = 0; z < Nt; ++z)
         store_C<P, NST, R, 10>(C[z], (side ? sTp : sTm) + z * TS, Ns, T(1), lane);
@@ -1034,8 +1060,8 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
       Acc C[NST], Cn[NST];
       zero_C<P, NST>(C);
       zero_C<P, NST>(Cn);
-      wave_gemm<P, NST, KSL, 16>(Fe, Uze + z * KPL * 16, C, lane);
-      wave_gemm<P, NST, KSL, 16>(Fn, Uzn + z * KPL * 16, Cn, lane);
+      wave_gemm<P, NST, KSL, 10>(Fe, Uze + z * DM::UZT, C, lane);
+      wave_gemm<P, NST, KSL, 10>(Fn, Uzn + z * DM::UZT, Cn, lane);
       store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
       store_C<P, NST, R, 10>(Cn, sTp + z * TS, Ns, T(1), lane);
     }
@@ -1206,7 +1232,7 @@ __global__ __launch_bounds__(64) void k_taylor(StepArgs<P> a, ClusterOffsets off
   for (int i = 1; i <= N; ++i)
 #pragma unroll
     for (int j = 0; j < DPL; ++j) d[i][j] = De[(i - 1) * KPL * 16 + lane + 64 * j];
-  T* Uzo = a.Uz + (size_t)e * Nt * KPL * 16;
+  T* Uzo = a.Uz + (size_t)e * DM::UZE;
 #pragma unroll
   for (int z = 0; z < Nt; ++z) {
     T cz[N + 1];
@@ -1219,7 +1245,8 @@ __global__ __launch_bounds__(64) void k_taylor(StepArgs<P> a, ClusterOffsets off
       T v = T(0);
 #pragma unroll
       for (int i = 0; i <= N; ++i) v += cz[i] * d[i][j];
-      Uzo[z * KPL * 16 + lane + 64 * j] = v;
+      const int idx = lane + 64 * j, l = idx >> 4, p = idx & 15;
+      if (l < L && p < 10) Uzo[z * DM::UZT + l * 10 + p] = v;
     }
   }
 }
