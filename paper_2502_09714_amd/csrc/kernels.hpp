@@ -401,12 +401,13 @@ template <int N, int P> struct FwdRegs {
 // Launch shapes of the two halves of the element update.  The prediction
 // keeps the derivatives in registers (45 values per lane at degree 4 in FP32)
 // with one LDS buffer; the volume half holds only per-point time integrals.
-// Degree 4 (c5 step, ms): FP32 prediction 93.3 at 4 wavefronts per SIMD
-// against 95.2 at 3; the split-BF16 one 82.2 at 3 against 90.6 at 4 (its
-// register budget at 4 spills).
+// Degree 4: 3 wavefronts per SIMD (151 registers).  At 4 the budget of 128
+// spills 22 registers per lane: the FP32 prediction ran 93.3 against 95.2 ms
+// on the 5.3 M-tet step, but its scratch traffic doubled the kernel's HBM
+// bytes (1.0e11 against 4.6e10 algorithmic); the split-BF16 one was slower
+// outright (90.6 against 82.2 ms).
 template <int N, int P> struct PredWaves {
-  static constexpr int value =
-      !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : (P == PREC_BF16 ? 3 : 4)));
+  static constexpr int value = !FwdRegs<N, P>::value ? 1 : (P == PREC_F64 ? 2 : (N <= 3 ? 5 : 3));
 };
 // (Split-BF16 volume at degree 4: 3 wavefronts per SIMD, where its 162
 // registers fit; at 4 the budget of 128 spills.)
