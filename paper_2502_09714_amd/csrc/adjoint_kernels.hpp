@@ -97,11 +97,11 @@ void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
     zero_C<P, NST>(C);
     zero_C<P, NST>(Cn);
     if (z < Nt) {
-      wave_gemm<P, NST, KSL, 10>(Fe, Uze + z * DM::UZT, C, lane);
-      wave_gemm<P, NST, KSL, 10>(Fn, Uzn + z * DM::UZT, Cn, lane);
+      wave_gemm<P, NST, KSL, 10, KSL, 16, false>(Fe, Uze + z * DM::UZT, C, lane);
+      wave_gemm<P, NST, KSL, 10, KSL, 16, false>(Fn, Uzn + z * DM::UZT, Cn, lane);
     } else {
-      wave_gemm<P, NST, KSL, 16>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
-      wave_gemm<P, NST, KSL, 16>(Fn, A.lam + (size_t)nb * KPL * 16, Cn, lane);
+      wave_gemm<P, NST, KSL, 16, KSL, 16, false>(Fe, A.lam + (size_t)e * KPL * 16, C, lane);
+      wave_gemm<P, NST, KSL, 16, KSL, 16, false>(Fn, A.lam + (size_t)nb * KPL * 16, Cn, lane);
     }
     store_C<P, NST, R, 10>(C, z < Nt ? sTm + z * TS : sLm, Ns, T(1), lane);
     store_C<P, NST, R, 10>(Cn, z < Nt ? sTp + z * TS : sLp, Ns, T(1), lane);

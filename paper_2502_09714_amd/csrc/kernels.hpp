@@ -1061,8 +1061,8 @@ void k_face_flux(StepArgs<P> a, const int* faces, long long nfaces, typename Pre
       Acc C[NST], Cn[NST];
       zero_C<P, NST>(C);
       zero_C<P, NST>(Cn);
-      wave_gemm<P, NST, KSL, 10>(Fe, Uze + z * DM::UZT, C, lane);
-      wave_gemm<P, NST, KSL, 10>(Fn, Uzn + z * DM::UZT, Cn, lane);
+      wave_gemm<P, NST, KSL, 10, KSL, 16, false>(Fe, Uze + z * DM::UZT, C, lane);
+      wave_gemm<P, NST, KSL, 10, KSL, 16, false>(Fn, Uzn + z * DM::UZT, Cn, lane);
       store_C<P, NST, R, 10>(C, sTm + z * TS, Ns, T(1), lane);
       store_C<P, NST, R, 10>(Cn, sTp + z * TS, Ns, T(1), lane);
     }

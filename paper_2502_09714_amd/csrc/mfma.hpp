@@ -157,17 +157,43 @@ template <int P> struct Accurate { static constexpr int value = P == PREC_BF16 ?
 // columns from NC on are zero (column NC is stored and zero, see bcol).
 // KSTEPS is a compile-time constant so that the loop unrolls and the A-fragment
 // loads are issued ahead of the matrix-core instructions that consume them.
+// PF false leaves the loads to the compiler's schedule (where B comes from HBM
+// as well and two independent products are interleaved by the caller).
 template <int P, int MT, int KSTEPS, int RS = Lds<typename Prec<P>::T>::RS, int KSTRIDE = KSTEPS,
-          int NC = 16>
+          int NC = 16, bool PF = true>
 __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
                                  const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT],
                                  int lane) {
   using PR = Prec<P>;
+  using AF = typename PR::AF;
+  if constexpr (!PF) {
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+      const AF b = PR::template loadB<RS, NC>(B, s, lane);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
+    }
+    return;
+  }
+  // A fragments of step s + PD requested before the products of step s (see
+  // wave_gemm2)
+  constexpr int PD = 2, NB = PD + 1;
+  AF a[NB][MT];
+#pragma unroll
+  for (int s = 0; s < PD && s < KSTEPS; ++s)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) a[s % NB][t] = Apk[((size_t)t * KSTRIDE + s) * 64 + lane];
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    typename PR::AF b = PR::template loadB<RS, NC>(B, s, lane);
+    if (s + PD < KSTEPS) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTRIDE + s) * 64 + lane], b, C[t]);
+      for (int t = 0; t < MT; ++t)
+        a[(s + PD) % NB][t] = Apk[((size_t)t * KSTRIDE + s + PD) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const AF b = PR::template loadB<RS, NC>(B, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(a[s % NB][t], b, C[t]);
   }
 }
 
@@ -178,17 +204,30 @@ __device__ inline void wave_gemm_shared_a(const typename Prec<P>::AF* __restrict
                                           const typename Prec<P>::T* B,
                                           typename Prec<P>::Acc (&C)[NZ][MT], int lane) {
   using PR = Prec<P>;
+  using AF = typename PR::AF;
+  // A and B fragments (both from L2/HBM here) one step ahead (see
+  // wave_gemm2); the NZ x MT products of a step cover their latency
+  constexpr int PD = 1, NB = PD + 1;
+  AF a[NB][MT], b[NB][NZ];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) a[0][t] = Apk[((size_t)t * KSTEPS) * 64 + lane];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) b[0][z] = PR::template loadB<RS>(B + z * BSTRIDE, 0, lane);
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    typename PR::AF b[NZ];
+    if (s + PD < KSTEPS) {
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) b[z] = PR::template loadB<RS>(B + z * BSTRIDE, s, lane);
+      for (int t = 0; t < MT; ++t)
+        a[(s + PD) % NB][t] = Apk[((size_t)t * KSTEPS + s + PD) * 64 + lane];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const typename PR::AF av = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) C[z][t] = PR::mma(av, b[z], C[z][t]);
+      for (int z = 0; z < NZ; ++z)
+        b[(s + PD) % NB][z] = PR::template loadB<RS>(B + z * BSTRIDE, s + PD, lane);
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) C[z][t] = PR::mma(a[s % NB][t], b[s % NB][z], C[z][t]);
   }
 }
 
@@ -199,12 +238,19 @@ __device__ inline void wave_gemm_tiles(const typename Prec<P>::AF* __restrict__ 
                                        const typename Prec<P>::T* B,
                                        typename Prec<P>::Acc (&C)[MT], int lane) {
   using PR = Prec<P>;
+  using AF = typename PR::AF;
+  // A fragments PD products ahead, in the order they are used (see wave_gemm2)
+  constexpr int NS = MT * KSTEPS, PD = 4, NB = PD + 1;
+  AF a[NB];
 #pragma unroll
-  for (int t = 0; t < MT; ++t)
+  for (int k = 0; k < PD && k < NS; ++k) a[k % NB] = Apk[(size_t)k * 64 + lane];
 #pragma unroll
-    for (int s = 0; s < KSTEPS; ++s)
-      C[t] = PR::mma(Apk[((size_t)t * KSTEPS + s) * 64 + lane], PR::template loadB<RS>(B, s, lane),
-                     C[t]);
+  for (int k = 0; k < NS; ++k) {
+    if (k + PD < NS) a[(k + PD) % NB] = Apk[(size_t)(k + PD) * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    const int t = k / KSTEPS, s = k % KSTEPS;
+    C[t] = PR::mma(a[k % NB], PR::template loadB<RS>(B, s, lane), C[t]);
+  }
 }
 
 // C += A x B for a B of 32 columns (two 16-column tiles, row stride RS): each
@@ -214,15 +260,31 @@ __device__ inline void wave_gemm2(const typename Prec<P>::AF* __restrict__ Apk,
                                   const typename Prec<P>::T* B, typename Prec<P>::Acc (&C)[MT][2],
                                   int lane) {
   using PR = Prec<P>;
+  using AF = typename PR::AF;
+  // A fragments come from L2/HBM: those of step s + PD are requested before
+  // the products of step s are issued (the scheduling fence keeps the
+  // compiler from sinking the loads down to their use), so that PD steps of
+  // matrix-core work cover their latency
+  constexpr int PD = 2, NB = PD + 1;
+  AF a[NB][MT];
+#pragma unroll
+  for (int s = 0; s < PD && s < KSTEPS; ++s)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) a[s % NB][t] = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    const typename PR::AF b0 = PR::template loadB<RS>(B, s, lane);
-    const typename PR::AF b1 = PR::template loadB<RS>(B + 16, s, lane);
+    if (s + PD < KSTEPS) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        a[(s + PD) % NB][t] = Apk[((size_t)t * KSTEPS + s + PD) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const AF b0 = PR::template loadB<RS>(B, s, lane);
+    const AF b1 = PR::template loadB<RS>(B + 16, s, lane);
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const typename PR::AF av = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
-      C[t][0] = PR::mma(av, b0, C[t][0]);
-      C[t][1] = PR::mma(av, b1, C[t][1]);
+      C[t][0] = PR::mma(a[s % NB][t], b0, C[t][0]);
+      C[t][1] = PR::mma(a[s % NB][t], b1, C[t][1]);
     }
   }
 }
@@ -258,11 +320,26 @@ __device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ A
                                       const typename Prec<P>::T* v, typename Prec<P>::Acc (&C)[MT],
                                       int lane) {
   using PR = Prec<P>;
+  using AF = typename PR::AF;
+  // A fragments of step s + PD requested before the products of step s (see
+  // wave_gemm2)
+  constexpr int PD = 2, NB = PD + 1;
+  AF a[NB][MT];
+#pragma unroll
+  for (int s = 0; s < PD && s < KSTEPS; ++s)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) a[s % NB][t] = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    typename PR::AF b = PR::loadB9(v, s, lane);
+    if (s + PD < KSTEPS) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) C[t] = PR::mma(Apk[((size_t)t * KSTEPS + s) * 64 + lane], b, C[t]);
+      for (int t = 0; t < MT; ++t)
+        a[(s + PD) % NB][t] = Apk[((size_t)t * KSTEPS + s + PD) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const AF b = PR::loadB9(v, s, lane);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) C[t] = PR::mma(a[s % NB][t], b, C[t]);
   }
 }
 
