@@ -25,6 +25,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// How many matrix-core steps ahead the helpers below request their A
+// fragments from L2/HBM (register cost: that many fragment sets per tile row)
+#ifndef DGD_PF_STEPS
+#define DGD_PF_STEPS 4
+#endif
+#ifndef DGD_PF_SHARED
+#define DGD_PF_SHARED 2
+#endif
+#ifndef DGD_PF_TILES
+#define DGD_PF_TILES 4
+#endif
+
 namespace dgd {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -177,7 +189,7 @@ __device__ inline void wave_gemm(const typename Prec<P>::AF* __restrict__ Apk,
   }
   // A fragments of step s + PD requested before the products of step s (see
   // wave_gemm2)
-  constexpr int PD = 2, NB = PD + 1;
+  constexpr int PD = DGD_PF_STEPS, NB = PD + 1;
   AF a[NB][MT];
 #pragma unroll
   for (int s = 0; s < PD && s < KSTEPS; ++s)
@@ -205,14 +217,17 @@ __device__ inline void wave_gemm_shared_a(const typename Prec<P>::AF* __restrict
                                           typename Prec<P>::Acc (&C)[NZ][MT], int lane) {
   using PR = Prec<P>;
   using AF = typename PR::AF;
-  // A and B fragments (both from L2/HBM here) one step ahead (see
+  // A and B fragments (both from L2/HBM here) PD steps ahead (see
   // wave_gemm2); the NZ x MT products of a step cover their latency
-  constexpr int PD = 1, NB = PD + 1;
+  constexpr int PD = DGD_PF_SHARED, NB = PD + 1;
   AF a[NB][MT], b[NB][NZ];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) a[0][t] = Apk[((size_t)t * KSTEPS) * 64 + lane];
+  for (int s = 0; s < PD && s < KSTEPS; ++s) {
 #pragma unroll
-  for (int z = 0; z < NZ; ++z) b[0][z] = PR::template loadB<RS>(B + z * BSTRIDE, 0, lane);
+    for (int t = 0; t < MT; ++t) a[s % NB][t] = Apk[((size_t)t * KSTEPS + s) * 64 + lane];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) b[s % NB][z] = PR::template loadB<RS>(B + z * BSTRIDE, s, lane);
+  }
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
     if (s + PD < KSTEPS) {
@@ -240,7 +255,7 @@ __device__ inline void wave_gemm_tiles(const typename Prec<P>::AF* __restrict__ 
   using PR = Prec<P>;
   using AF = typename PR::AF;
   // A fragments PD products ahead, in the order they are used (see wave_gemm2)
-  constexpr int NS = MT * KSTEPS, PD = 4, NB = PD + 1;
+  constexpr int NS = MT * KSTEPS, PD = DGD_PF_TILES, NB = PD + 1;
   AF a[NB];
 #pragma unroll
   for (int k = 0; k < PD && k < NS; ++k) a[k % NB] = Apk[(size_t)k * 64 + lane];
@@ -265,7 +280,7 @@ __device__ inline void wave_gemm2(const typename Prec<P>::AF* __restrict__ Apk,
   // the products of step s are issued (the scheduling fence keeps the
   // compiler from sinking the loads down to their use), so that PD steps of
   // matrix-core work cover their latency
-  constexpr int PD = 2, NB = PD + 1;
+  constexpr int PD = DGD_PF_STEPS, NB = PD + 1;
   AF a[NB][MT];
 #pragma unroll
   for (int s = 0; s < PD && s < KSTEPS; ++s)
@@ -323,7 +338,7 @@ __device__ inline void wave_gemm_col9(const typename Prec<P>::AF* __restrict__ A
   using AF = typename PR::AF;
   // A fragments of step s + PD requested before the products of step s (see
   // wave_gemm2)
-  constexpr int PD = 2, NB = PD + 1;
+  constexpr int PD = DGD_PF_STEPS, NB = PD + 1;
   AF a[NB][MT];
 #pragma unroll
   for (int s = 0; s < PD && s < KSTEPS; ++s)
