@@ -231,6 +231,9 @@ def run_adjoint(w, prec, steps, every, observed=False):
            "backward_kernel_ms_per_step": {k: float(ms[i]) / steps for i, k in enumerate(KERNELS)
                                            if launches[i] > 0},
            "steps": steps, "checkpoint_every": every,
+           # the replay kept each segment's time-point states (else the
+           # adjoint recomputes the prediction per step)
+           "time_points_kept": bool(launches[KERNELS.index("adj_predict_recompute")] == 0),
            "finite": bool(np.isfinite(gmu).all() and np.isfinite(gcd).all())}
     return out, (gmu, gcd, obs, U0, base)
 
@@ -510,7 +513,10 @@ def main():
                     help="precisions whose checkpointed adjoint is timed on the step workload "
                          "('' for none)")
     ap.add_argument("--checkpoint-every", type=int, default=5)
-    ap.add_argument("--adjoint-runs", default="c4:400:20,c3:200:20,c3:200:20:bf16",
+    # c3 in FP32 with checkpoints every 10 steps: a segment's time-point
+    # states (11 GB per step) then fit in HBM beside the checkpoints, and the
+    # adjoint reads them instead of repeating the prediction
+    ap.add_argument("--adjoint-runs", default="c4:400:20,c3:200:10,c3:200:20:bf16",
                     help="checkpointed adjoint runs workload:steps:every[:bf16] (FP32 "
                          "adjoint arithmetic; bf16: split-BF16 forward) ('' for none)")
     ap.add_argument("--adjoint-fd", type=int, default=0,
