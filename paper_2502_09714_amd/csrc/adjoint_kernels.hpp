@@ -50,11 +50,12 @@ template <int P> struct AdjArgs {
 // both traces, written to gtr[face][side][z][Ns][10] (lifted by k_adj_volume),
 // and of both sides' mu0, summed over the face points with their weights into
 // gmuf[face][side].
-// FP64: two wavefronts per SIMD at the price of a few spilled registers (the
-// unconstrained form needs more than one wavefront's share of the register
-// file); FP32 keeps its registers (forcing four spills far more).
+// FP64 below degree 4: two wavefronts per SIMD at the price of a few spilled
+// registers (the unconstrained form needs more than one wavefront's share of
+// the register file); FP32: at least two, which its registers fit without
+// spilling (forcing four spills far more).
 template <int N, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P == PREC_F64 && N <= 3 ? 2 : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P != PREC_F64 || N <= 3 ? 2 : 1)))
 void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
   using PR = Prec<P>;
   using T = typename PR::T;
@@ -90,8 +91,22 @@ void k_adj_face(AdjArgs<P> A, const int* faces, long long nfaces) {
       a.Fpk + (size_t)(nf * 6 + (inner ? conn_nperm(w) : sp)) * NST * KSL * 64;
   const T* Uze = a.Uz + (size_t)e * DM::UZE;
   const T* Uzn = a.Uz + (size_t)nb * DM::UZE;
+  if constexpr (FaceSharedA<P>::value) {
+    // the time-point states ([L][10]) one side after the other, all time
+    // points together: each trace-matrix fragment is loaded once per side
+    Acc Cz[Nt][NST];
 #pragma unroll
-  for (int z = 0; z <= Nt; ++z) {
+    for (int side = 0; side < 2; ++side) {
+#pragma unroll
+      for (int z = 0; z < Nt; ++z) zero_C<P, NST>(Cz[z]);
+      wave_gemm_shared_a<P, NST, KSL, Nt, 10, DM::UZT>(side ? Fn : Fe, side ? Uzn : Uze, Cz, lane);
+#pragma unroll
+      for (int z = 0; z < Nt; ++z)
+        store_C<P, NST, R, 10>(Cz[z], (side ? sTp : sTm) + z * TS, Ns, T(1), lane);
+    }
+  }
+#pragma unroll
+  for (int z = FaceSharedA<P>::value ? Nt : 0; z <= Nt; ++z) {
     // z < Nt: time-point states ([L][10]); z = Nt: lambda^{n+1} ([KPL][16])
     Acc C[NST], Cn[NST];
     zero_C<P, NST>(C);
@@ -211,9 +226,9 @@ __global__ __launch_bounds__(64) void k_adj_lift(AdjArgs<P> A) {
     }
     if (f < 3) load_face(f + 1);
     __syncthreads();
-#pragma unroll
-    for (int z = 0; z < Nt; ++z)
-      wave_gemm<P, MT, KSN>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sG + z * GB, Cz[z], lane);
+    // one lift matrix for all time points: each of its fragments is loaded once
+    wave_gemm_shared_a<P, MT, KSN, Nt, R, GB>(a.Lpk + (size_t)(f * 6 + sp) * MT * KSN * 64, sG, Cz,
+                                             lane);
   }
 #pragma unroll
   for (int z = 0; z < Nt; ++z)

@@ -217,7 +217,7 @@ __device__ inline void wave_gemm_shared_a(const typename Prec<P>::AF* __restrict
                                           typename Prec<P>::Acc (&C)[NZ][MT], int lane) {
   using PR = Prec<P>;
   using AF = typename PR::AF;
-  // A and B fragments (both from L2/HBM here) PD steps ahead (see
+  // A and B fragments (A from L2/HBM, B from HBM or LDS) PD steps ahead (see
   // wave_gemm2); the NZ x MT products of a step cover their latency
   constexpr int PD = DGD_PF_SHARED, NB = PD + 1;
   AF a[NB][MT], b[NB][NZ];
