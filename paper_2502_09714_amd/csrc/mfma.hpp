@@ -25,8 +25,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// How many matrix-core steps ahead the helpers below request their A
-// fragments from L2/HBM (register cost: that many fragment sets per tile row)
+// Depths of the register rings in the helpers below: how far ahead of its use
+// a fragment is requested from L2/HBM (each slot costs one fragment per tile
+// row in registers).
+//   DGD_PF_STEPS   matrix-core steps, A only: wave_gemm, wave_gemm2, wave_gemm_col9
+//   DGD_PF_SHARED  matrix-core steps, A and B: wave_gemm_shared_a
+//   DGD_PF_TILES   single products, A only: wave_gemm_tiles
 #ifndef DGD_PF_STEPS
 #define DGD_PF_STEPS 4
 #endif
